@@ -1,0 +1,224 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module builds initial data u_0 for the conservation law (1.1) and the random
+perturbation coefficients of the Kelvin--Helmholtz shear layer (Section 3). It holds none
+of the finite-volume scheme's arithmetic: no reconstruction, flux, divergence, time step or
+statistic is computed here, only the initial states the scheme starts from.
+
+Random numbers come from one counter-based generator, SplitMix64 (G. L. Steele, D. Lea,
+C. H. Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014). Draw ``j`` of
+sample ``s`` under seed ``seed`` is ``mix64(seed + G * (s * 64 + j + 1))`` with the golden
+gamma ``G = 0x9E3779B97F4A7C15``; the top 53 bits give a uniform double in [0, 1).
+
+State layout (for every builder): float64, structure of arrays
+``[batch][field][nz][ny][nx]`` with x fastest; Euler fields are (rho, m_x[, m_y[, m_z]], E).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+MASK64 = (1 << 64) - 1
+
+__all__ = [
+    "mix64", "uniform_draws", "kh_coefficients", "kh3d_coefficients", "kh_delta",
+    "sod_state", "riemann_state_1d", "kh2d_state", "kh3d_state", "constant_state",
+    "random_smooth_state", "sine_state_scalar", "cell_centres",
+]
+
+
+def mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on uint64 (wrapping arithmetic)."""
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_draws(seed: int, samples, n_draws: int) -> np.ndarray:
+    """Uniform doubles in [0,1): array [len(samples)][n_draws]; draw j of sample s."""
+    samples = np.atleast_1d(np.asarray(samples, dtype=np.uint64))
+    j = np.arange(n_draws, dtype=np.uint64)
+    ctr = samples[:, None] * np.uint64(64) + j[None, :] + np.uint64(1)
+    with np.errstate(over="ignore"):
+        x = np.uint64(seed & MASK64) + np.uint64(GOLDEN_GAMMA) * ctr
+    z = mix64(x)
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def kh_coefficients(seed: int, samples, modes: int = 10):
+    """Perturbation coefficients c_k ~ U[0,1), phi_k ~ U[0, 2 pi) for k = 1..modes.
+
+    Returns (c, phi), each [len(samples)][modes]. c uses draws 0..modes-1 and phi draws
+    modes..2*modes-1 of each sample.
+    """
+    u = uniform_draws(seed, samples, 2 * modes)
+    return u[:, :modes].copy(), (2.0 * np.pi) * u[:, modes:]
+
+
+def kh3d_coefficients(seed: int, samples, modes: int = 10):
+    """Two independent sets (x and z modes) for the 3D shear layer: (cx, phix, cz, phiz)."""
+    u = uniform_draws(seed, samples, 4 * modes)
+    m = modes
+    return (u[:, :m].copy(), (2.0 * np.pi) * u[:, m:2 * m],
+            u[:, 2 * m:3 * m].copy(), (2.0 * np.pi) * u[:, 3 * m:4 * m])
+
+
+def cell_centres(n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    return lo + (np.arange(n, dtype=np.float64) + 0.5) * ((hi - lo) / n)
+
+
+def kh_delta(c: np.ndarray, phi: np.ndarray, x: np.ndarray, a: float = 0.01) -> np.ndarray:
+    """Interface displacement delta(x) = a * sum_k c_k sin(2 pi k x + phi_k), summed k = 1.. in order.
+
+    c, phi: [batch][modes]; x: [nx]. Returns [batch][nx].
+    """
+    c = np.atleast_2d(c)
+    phi = np.atleast_2d(phi)
+    acc = np.zeros((c.shape[0], x.shape[0]), dtype=np.float64)
+    for k in range(c.shape[1]):
+        acc = acc + c[:, k:k + 1] * np.sin((2.0 * np.pi * (k + 1)) * x[None, :] + phi[:, k:k + 1])
+    return a * acc
+
+
+def _euler_conserved(rho, u, v, w, p, gamma, dim):
+    gm1 = gamma - 1.0
+    if dim == 1:
+        ke = 0.5 * (rho * (u * u))
+        return [rho, rho * u, p / gm1 + ke]
+    if dim == 2:
+        ke = 0.5 * (rho * (u * u + v * v))
+        return [rho, rho * u, rho * v, p / gm1 + ke]
+    ke = 0.5 * (rho * (u * u + v * v + w * w))
+    return [rho, rho * u, rho * v, rho * w, p / gm1 + ke]
+
+
+def riemann_state_1d(n: int, left, right, gamma: float = 1.4, x0: float = 0.5) -> np.ndarray:
+    """1D Euler Riemann initial data: primitive (rho, u, p) left/right of x0. [1][3][1][1][n]."""
+    x = cell_centres(n)
+    lf = x < x0
+    rho = np.where(lf, left[0], right[0])
+    u = np.where(lf, left[1], right[1])
+    p = np.where(lf, left[2], right[2])
+    f = _euler_conserved(rho, u, None, None, p, gamma, 1)
+    return np.stack(f)[None, :, None, None, :].astype(np.float64)
+
+
+def sod_state(n: int = 1024, gamma: float = 1.4) -> np.ndarray:
+    """Sod shock tube on [0,1]: (1, 0, 1) | (0.125, 0, 0.1) split at x = 0.5."""
+    return riemann_state_1d(n, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), gamma)
+
+
+def _band_fraction(y_lo, y_hi, i1, i2, inv_dy):
+    """Fraction of the cell [y_lo, y_hi] inside the band (i1, i2) (volume fraction)."""
+    f = (np.minimum(y_hi, i2) - np.maximum(y_lo, i1)) * inv_dy
+    return np.minimum(1.0, np.maximum(0.0, f))
+
+
+def kh2d_state(n: int, c: np.ndarray, phi: np.ndarray, gamma: float = 1.4, a: float = 0.01,
+               ny: int | None = None) -> np.ndarray:
+    """2D Kelvin--Helmholtz shear layer on the periodic unit square.
+
+    p = 2.5 and v = 0 everywhere; rho = 2, u = 0.5 inside the band 0.25 + delta(x) < y <
+    0.75 + delta(x), rho = 1, u = -0.5 outside. Each cell takes the conserved state
+    U_out + f (U_in - U_out), with f the fraction of its y-extent (at the x-centre) inside the
+    band. Returns [batch][4][1][ny][nx].
+    """
+    nx = n
+    ny = n if ny is None else ny
+    c = np.atleast_2d(c)
+    phi = np.atleast_2d(phi)
+    xc = cell_centres(nx)
+    dy = 1.0 / ny
+    yj = np.arange(ny, dtype=np.float64)
+    y_lo = (yj * dy)[None, :, None]
+    y_hi = ((yj + 1.0) * dy)[None, :, None]
+    delta = kh_delta(c, phi, xc, a)[:, None, :]          # [b][1][nx]
+    f = _band_fraction(y_lo, y_hi, 0.25 + delta, 0.75 + delta, float(ny))  # [b][ny][nx]
+    uin = _euler_conserved(2.0, 0.5, 0.0, 0.0, 2.5, gamma, 2)
+    uout = _euler_conserved(1.0, -0.5, 0.0, 0.0, 2.5, gamma, 2)
+    out = np.empty((c.shape[0], 4, 1, ny, nx), dtype=np.float64)
+    for q in range(4):
+        out[:, q, 0] = uout[q] + f * (uin[q] - uout[q])
+    return out
+
+
+def kh3d_state(n: int, cx, phix, cz, phiz, gamma: float = 1.4, a: float = 0.01) -> np.ndarray:
+    """3D shear layer in y on the periodic unit cube, interface delta(x) + delta(z), w = 0.
+
+    Returns [batch][5][n][n][n]. Built one z-plane at a time to bound host memory.
+    """
+    cx = np.atleast_2d(cx)
+    b = cx.shape[0]
+    xc = cell_centres(n)
+    dx_ = kh_delta(cx, phix, xc, a)          # [b][n] over x
+    dz_ = kh_delta(cz, phiz, xc, a)          # [b][n] over z
+    dy = 1.0 / n
+    yj = np.arange(n, dtype=np.float64)
+    y_lo = (yj * dy)[:, None]
+    y_hi = ((yj + 1.0) * dy)[:, None]
+    uin = _euler_conserved(2.0, 0.5, 0.0, 0.0, 2.5, gamma, 3)
+    uout = _euler_conserved(1.0, -0.5, 0.0, 0.0, 2.5, gamma, 3)
+    out = np.empty((b, 5, n, n, n), dtype=np.float64)
+    for s in range(b):
+        for k in range(n):
+            delta = (dx_[s] + dz_[s, k])[None, :]
+            f = _band_fraction(y_lo, y_hi, 0.25 + delta, 0.75 + delta, float(n))
+            for q in range(5):
+                out[s, q, k] = uout[q] + f * (uin[q] - uout[q])
+    return out
+
+
+def constant_state(shape_cells, values, batch: int = 1) -> np.ndarray:
+    """Every cell equal to ``values`` (one per field). shape_cells = (nz, ny, nx)."""
+    nz, ny, nx = shape_cells
+    vals = np.asarray(values, dtype=np.float64)
+    out = np.empty((batch, vals.size, nz, ny, nx), dtype=np.float64)
+    out[:] = vals[None, :, None, None, None]
+    return out
+
+
+def random_smooth_state(seed: int, shape_cells, dim: int, batch: int = 1, gamma: float = 1.4,
+                        amp: float = 0.1, modes: int = 3) -> np.ndarray:
+    """Smooth periodic Euler data: rho, u, v, w, p each a sum of random low Fourier modes.
+
+    rho and p stay within 1 +- amp*modes, so the data is physical for amp*modes < 1. The
+    velocities have amplitude 4*amp*modes, enough to make wave speeds of both signs appear
+    at faces. Used for short parity runs that exercise every branch of the fluxes.
+    """
+    nz, ny, nx = shape_cells
+    z = np.arange(nz, dtype=np.float64)[:, None, None] / nz
+    y = np.arange(ny, dtype=np.float64)[None, :, None] / ny
+    x = np.arange(nx, dtype=np.float64)[None, None, :] / nx
+    per = 5 * modes * 2
+    draws = uniform_draws(seed, np.arange(batch), per)
+    out = np.empty((batch, dim + 2, nz, ny, nx), dtype=np.float64)
+    for s in range(batch):
+        fields = []
+        for v in range(5):
+            acc = np.zeros((nz, ny, nx))
+            for m in range(modes):
+                a_m, ph = draws[s, 2 * (v * modes + m)], draws[s, 2 * (v * modes + m) + 1]
+                k = m + 1
+                arg = k * x + (k * y if dim >= 2 else 0.0) + (k * z if dim == 3 else 0.0)
+                acc = acc + (2.0 * a_m - 1.0) * np.sin(2.0 * np.pi * (arg + ph))
+            fields.append(amp * acc)
+        rho = 1.0 + fields[0]
+        p = 1.0 + fields[4]
+        u, v_, w = 4.0 * fields[1], 4.0 * fields[2], 4.0 * fields[3]
+        out[s] = np.stack(_euler_conserved(rho, u, v_, w, p, gamma, dim))
+    return out
+
+
+def sine_state_scalar(n: int, k: int = 1, amp: float = 1.0, offset: float = 0.0,
+                      dim: int = 1) -> np.ndarray:
+    """Scalar u(x) = offset + amp sin(2 pi k x) at cell centres, constant in y and z."""
+    x = cell_centres(n)
+    u = offset + amp * np.sin(2.0 * np.pi * k * x)
+    if dim == 1:
+        return u[None, None, None, None, :].copy()
+    if dim == 2:
+        return np.broadcast_to(u[None, None, None, None, :], (1, 1, 1, n, n)).copy()
+    return np.broadcast_to(u[None, None, None, None, :], (1, 1, n, n, n)).copy()

@@ -1,0 +1,671 @@
+/*
+ * fv_oracle.c -- plain, slow FP64 CPU reference ("the oracle") for the explicit
+ * finite-volume method of Lye, "Alsvinn: A fast multi-GPGPU finite volume solver with a
+ * strong emphasis on reproducibility" (arXiv:1912.07645).
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark load this file. The GPU library shares no code, header, table or
+ * constant with it.
+ *
+ * What it computes:
+ *   - the conservation law u_t + div F(u) = 0 (eq. 1.1) for linear advection, Burgers and
+ *     the compressible Euler equations (gamma law) in 1, 2 or 3 space dimensions;
+ *   - its semi-discrete finite-volume form (eq. 2.1): d/dt U_i = -sum_k (F_{i+1/2 e_k} -
+ *     F_{i-1/2 e_k}) / dx_k, with the numerical fluxes (Rusanov, HLL, HLLC), the
+ *     reconstructions (piecewise constant, MUSCL with minmod, third-order WENO) and the SSP
+ *     Runge--Kutta time steppers (forward Euler, SSP-RK2, SSP-RK3) named in Section 2.1;
+ *   - a CFL time step from the maximum wave speed, and the Monte Carlo statistics named in
+ *     Section 2.2 (per-cell mean and variance over samples, two-point structure functions),
+ *     and the single- and multi-level Monte Carlo estimators of Section 2.2.
+ *
+ * Every pass is a separate loop over plain arrays in the order the method takes it:
+ * ghost fill into a padded copy, reconstruction of the two face values of every cell,
+ * numerical flux at every face, flux-difference divergence, Runge--Kutta combination.
+ * Nothing is blocked, fused or reordered. Each floating-point expression is written with
+ * explicit parentheses in the evaluation order of the arithmetic contract (no FMA, no
+ * reassociation; compile with -ffp-contract=off and without fast-math).
+ *
+ * Readings where the paper is silent (it names the schemes but prints no formulas):
+ *   - reconstruction acts component-wise on the conserved variables;
+ *   - WENO3 uses the Jiang--Shu smoothness indicators, eps = 1e-6, power 2, linear weights
+ *     (2/3, 1/3), written with one division: w = (2 t1 q0 + t0 q1) / (2 t1 + t0);
+ *   - HLL and HLLC take Davis wave-speed estimates SL = min(uL-cL, uR-cR),
+ *     SR = max(uL+cL, uR+cR); HLLC is Toro--Spruce--Speares with the star state of
+ *     Toro's book (ties: SL >= 0 takes FL, SR <= 0 takes FR, S* >= 0 takes the left star);
+ *   - the SSP Runge--Kutta stages are written in increment form
+ *     U^(s) = U^n + beta_s ((U^(s-1) - U^n) + dt L(U^(s-1))), beta = {1}, {1, 1/2},
+ *     {1, 1/4, 2/3}, algebraically the Shu--Osher form;
+ *   - dt = cfl / max_cells max_d (|u_d| + c) / dx_d, the last step clipped to end at T;
+ *   - transmissive boundaries copy the edge cell into every ghost layer.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------- problem description */
+
+enum { OC_EQ_ADVECTION = 0, OC_EQ_BURGERS = 1, OC_EQ_EULER = 2 };
+enum { OC_FLUX_RUSANOV = 0, OC_FLUX_HLL = 1, OC_FLUX_HLLC = 2 };
+enum { OC_REC_FIRST = 0, OC_REC_MUSCL = 1, OC_REC_WENO3 = 2 };
+enum { OC_INT_FE = 0, OC_INT_RK2 = 1, OC_INT_RK3 = 2 };
+enum { OC_BC_PERIODIC = 0, OC_BC_TRANSMISSIVE = 1 };
+enum { OC_OK = 0, OC_EINVAL = 1, OC_ENOTSUP = 2, OC_ENOMEM = 3,
+       OC_ENONPHYS = 5, OC_EMAXSTEPS = 6, OC_ECFL = 7 };
+
+#define OC_MAXF 5
+
+typedef struct {
+    int32_t dim;
+    int32_t eq;
+    int32_t flux;
+    int32_t recon;
+    int32_t integrator;
+    int32_t bc[3];
+    int64_t n[3];
+    double lo[3];
+    double hi[3];
+    double gamma;
+    double vel[3];
+} oc_problem;
+
+int oc_num_fields(const oc_problem* P)
+{
+    return P->eq == OC_EQ_EULER ? P->dim + 2 : 1;
+}
+
+static int64_t cells_of(const oc_problem* P)
+{
+    return P->n[0] * P->n[1] * P->n[2];
+}
+
+/* Two ghost layers on every active axis: the widest stencil (MUSCL, WENO3) reaches two
+ * cells beyond a face; piecewise-constant reconstruction uses only the first layer. */
+static int ghost_width(const oc_problem* P)
+{
+    (void)P;
+    return 2;
+}
+
+int oc_validate(const oc_problem* P)
+{
+    if (P->dim < 1 || P->dim > 3) return OC_EINVAL;
+    for (int k = 0; k < 3; ++k) {
+        if (P->n[k] < 1) return OC_EINVAL;
+        if (k >= P->dim && P->n[k] != 1) return OC_EINVAL;
+        if (k < P->dim && !(P->hi[k] > P->lo[k])) return OC_EINVAL;
+        if (P->bc[k] != OC_BC_PERIODIC && P->bc[k] != OC_BC_TRANSMISSIVE) return OC_EINVAL;
+    }
+    if (P->eq < 0 || P->eq > 2) return OC_EINVAL;
+    if (P->flux < 0 || P->flux > 2) return OC_EINVAL;
+    if (P->recon < 0 || P->recon > 2) return OC_EINVAL;
+    if (P->integrator < 0 || P->integrator > 2) return OC_EINVAL;
+    if (P->flux == OC_FLUX_HLLC && P->eq != OC_EQ_EULER) return OC_ENOTSUP;
+    if (P->eq == OC_EQ_EULER && !(P->gamma > 1.0)) return OC_EINVAL;
+    return OC_OK;
+}
+
+/* dx_k^{-1}, computed as n_k / (hi_k - lo_k) */
+static double inv_dx(const oc_problem* P, int k)
+{
+    return (double)P->n[k] / (P->hi[k] - P->lo[k]);
+}
+
+static double dmax(double a, double b) { return (a > b) ? a : b; }
+static double dmin(double a, double b) { return (a < b) ? a : b; }
+
+/* ---------------------------------------------------------------- physical fluxes */
+
+/* Euler primitive quantities of one conserved state (rho, m_1..m_d, E). */
+typedef struct {
+    double ir;        /* 1 / rho */
+    double u[3];      /* velocity */
+    double p;         /* pressure */
+    double c;         /* sound speed */
+} oc_prim;
+
+static oc_prim euler_prim(const double* U, int dim, double gamma, double gm1)
+{
+    oc_prim w;
+    w.ir = 1.0 / U[0];
+    w.u[0] = w.u[1] = w.u[2] = 0.0;
+    for (int k = 0; k < dim; ++k) w.u[k] = U[1 + k] * w.ir;
+    double ke = U[1] * w.u[0];
+    if (dim >= 2) ke = ke + (U[2] * w.u[1]);
+    if (dim >= 3) ke = ke + (U[3] * w.u[2]);
+    ke = 0.5 * ke;
+    w.p = gm1 * (U[dim + 1] - ke);
+    w.c = sqrt((gamma * w.p) * w.ir);
+    return w;
+}
+
+/* Euler flux in direction nd of the state U with primitives w. */
+static void euler_flux(const double* U, const oc_prim* w, int dim, int nd, double* F)
+{
+    double un = w->u[nd];
+    F[0] = U[1 + nd];
+    for (int k = 0; k < dim; ++k) {
+        if (k == nd) F[1 + k] = (U[1 + nd] * un) + w->p;
+        else         F[1 + k] = U[1 + k] * un;
+    }
+    F[dim + 1] = (U[dim + 1] + w->p) * un;
+}
+
+/* ---------------------------------------------------------------- numerical fluxes */
+
+/* Numerical flux across a face with normal direction nd, from the reconstructed states
+ * UL (left of the face) and UR (right of the face). */
+void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const double* UR,
+                       double* Fh)
+{
+    const int nf = oc_num_fields(P);
+    if (P->eq == OC_EQ_EULER) {
+        const int dim = P->dim;
+        const double gamma = P->gamma;
+        const double gm1 = gamma - 1.0;
+        oc_prim wl = euler_prim(UL, dim, gamma, gm1);
+        oc_prim wr = euler_prim(UR, dim, gamma, gm1);
+        double FL[OC_MAXF], FR[OC_MAXF];
+        euler_flux(UL, &wl, dim, nd, FL);
+        euler_flux(UR, &wr, dim, nd, FR);
+        const double uL = wl.u[nd], uR = wr.u[nd];
+        if (P->flux == OC_FLUX_RUSANOV) {
+            double s = dmax(fabs(uL) + wl.c, fabs(uR) + wr.c);
+            for (int q = 0; q < nf; ++q)
+                Fh[q] = 0.5 * ((FL[q] + FR[q]) - (s * (UR[q] - UL[q])));
+            return;
+        }
+        double SL = dmin(uL - wl.c, uR - wr.c);
+        double SR = dmax(uL + wl.c, uR + wr.c);
+        if (SL >= 0.0) { for (int q = 0; q < nf; ++q) Fh[q] = FL[q]; return; }
+        if (SR <= 0.0) { for (int q = 0; q < nf; ++q) Fh[q] = FR[q]; return; }
+        if (P->flux == OC_FLUX_HLL) {
+            for (int q = 0; q < nf; ++q)
+                Fh[q] = (((SR * FL[q]) - (SL * FR[q])) + ((SL * SR) * (UR[q] - UL[q])))
+                        / (SR - SL);
+            return;
+        }
+        /* HLLC: contact speed S* and the star state on the side it selects. */
+        double DL = UL[0] * (SL - uL);
+        double DR = UR[0] * (SR - uR);
+        double num = (wr.p - wl.p) + ((UL[1 + nd] * (SL - uL)) - (UR[1 + nd] * (SR - uR)));
+        double den = DL - DR;
+        double Ss = num / den;
+        const double* UK; const double* FK; const oc_prim* wK; double SK, DK;
+        if (Ss >= 0.0) { UK = UL; FK = FL; wK = &wl; SK = SL; DK = DL; }
+        else           { UK = UR; FK = FR; wK = &wr; SK = SR; DK = DR; }
+        double uK = wK->u[nd];
+        double f = DK / (SK - Ss);
+        double Us[OC_MAXF];
+        Us[0] = f;
+        for (int k = 0; k < dim; ++k)
+            Us[1 + k] = (k == nd) ? (f * Ss) : (f * wK->u[k]);
+        Us[dim + 1] = f * ((UK[dim + 1] * wK->ir) + ((Ss - uK) * (Ss + (wK->p / DK))));
+        for (int q = 0; q < nf; ++q)
+            Fh[q] = FK[q] + (SK * (Us[q] - UK[q]));
+        return;
+    }
+    /* scalar equations */
+    double uL = UL[0], uR = UR[0];
+    double FL, FR, s, SL, SR;
+    if (P->eq == OC_EQ_BURGERS) {
+        FL = 0.5 * (uL * uL);
+        FR = 0.5 * (uR * uR);
+        s = dmax(fabs(uL), fabs(uR));
+        SL = dmin(uL, uR);
+        SR = dmax(uL, uR);
+    } else {
+        double a = P->vel[nd];
+        FL = a * uL;
+        FR = a * uR;
+        s = fabs(a);
+        SL = a;
+        SR = a;
+    }
+    if (P->flux == OC_FLUX_RUSANOV) {
+        Fh[0] = 0.5 * ((FL + FR) - (s * (uR - uL)));
+        return;
+    }
+    if (SL >= 0.0) { Fh[0] = FL; return; }
+    if (SR <= 0.0) { Fh[0] = FR; return; }
+    Fh[0] = (((SR * FL) - (SL * FR)) + ((SL * SR) * (uR - uL))) / (SR - SL);
+}
+
+/* ---------------------------------------------------------------- reconstruction */
+
+/* minmod of two one-sided differences (sign tests, no product). */
+static double minmod(double a, double b)
+{
+    if (a > 0.0 && b > 0.0) return dmin(a, b);
+    if (a < 0.0 && b < 0.0) return dmax(a, b);
+    return 0.0;
+}
+
+/* Third-order WENO value at the face between b and c, from the cells (a, b, c):
+ * candidates q0 = (b + c)/2 on {b, c} and q1 = (3b - a)/2 on {a, b}, smoothness
+ * beta0 = (c-b)^2, beta1 = (b-a)^2, linear weights 2/3 and 1/3, eps = 1e-6, power 2. */
+double oc_weno3(double a, double b, double c)
+{
+    const double eps = 1e-6;
+    double d0 = b - a;
+    double d1 = c - b;
+    double t0 = eps + (d1 * d1);
+    t0 = t0 * t0;
+    double t1 = eps + (d0 * d0);
+    t1 = t1 * t1;
+    double q0 = 0.5 * (b + c);
+    double q1 = (1.5 * b) - (0.5 * a);
+    return (((2.0 * t1) * q0) + (t0 * q1)) / ((2.0 * t1) + t0);
+}
+
+/* Face values of the cell with stencil values (um, u0, up) = (U_{i-1}, U_i, U_{i+1}):
+ * *minus = value at i-1/2, *plus = value at i+1/2. */
+static void reconstruct(int recon, double um, double u0, double up, double* minus, double* plus)
+{
+    if (recon == OC_REC_FIRST) {
+        *minus = u0;
+        *plus = u0;
+    } else if (recon == OC_REC_MUSCL) {
+        double sigma = minmod(u0 - um, up - u0);
+        *plus = u0 + (0.5 * sigma);
+        *minus = u0 - (0.5 * sigma);
+    } else {
+        *plus = oc_weno3(um, u0, up);
+        *minus = oc_weno3(up, u0, um);
+    }
+}
+
+/* ---------------------------------------------------------------- one right-hand side */
+
+static int64_t map_index(int64_t i, int64_t n, int bc)
+{
+    if (bc == OC_BC_PERIODIC) {
+        int64_t r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+/* Padded extents: g ghost layers on each side of every active axis. */
+typedef struct {
+    int64_t m[3];     /* padded sizes */
+    int g[3];         /* ghost width per axis (0 on inactive axes) */
+} oc_pad;
+
+static oc_pad pad_of(const oc_problem* P)
+{
+    oc_pad pd;
+    int g = ghost_width(P);
+    for (int k = 0; k < 3; ++k) {
+        pd.g[k] = (k < P->dim) ? g : 0;
+        pd.m[k] = P->n[k] + 2 * pd.g[k];
+    }
+    return pd;
+}
+
+static int64_t pidx(const oc_pad* pd, int64_t i, int64_t j, int64_t k)
+{
+    return ((k + pd->g[2]) * pd->m[1] + (j + pd->g[1])) * pd->m[0] + (i + pd->g[0]);
+}
+
+/* Step 1: ghost-cell fill. Copy one sample U[f][cells] into padded arrays, filling each
+ * ghost cell from the interior cell that the boundary condition maps it to. */
+static void ghost_fill(const oc_problem* P, const oc_pad* pd, const double* U, double* W)
+{
+    const int nf = oc_num_fields(P);
+    const int64_t N = cells_of(P);
+    const int64_t PN = pd->m[0] * pd->m[1] * pd->m[2];
+    for (int f = 0; f < nf; ++f) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t kk = 0; kk < pd->m[2]; ++kk)
+            for (int64_t jj = 0; jj < pd->m[1]; ++jj)
+                for (int64_t ii = 0; ii < pd->m[0]; ++ii) {
+                    int64_t i = map_index(ii - pd->g[0], P->n[0], P->bc[0]);
+                    int64_t j = map_index(jj - pd->g[1], P->n[1], P->bc[1]);
+                    int64_t k = map_index(kk - pd->g[2], P->n[2], P->bc[2]);
+                    W[f * PN + (kk * pd->m[1] + jj) * pd->m[0] + ii] =
+                        U[f * N + (k * P->n[1] + j) * P->n[0] + i];
+                }
+    }
+}
+
+/* L(U) = -sum_k (F_{i+1/2 e_k} - F_{i-1/2 e_k}) / dx_k for one sample (eq. 2.1). */
+int oc_rhs(const oc_problem* P, const double* U, double* rhs)
+{
+    int st = oc_validate(P);
+    if (st) return st;
+    const int nf = oc_num_fields(P);
+    const int dim = P->dim;
+    const int64_t N = cells_of(P);
+    const int64_t nx = P->n[0], ny = P->n[1], nz = P->n[2];
+    oc_pad pd = pad_of(P);
+    const int64_t PN = pd.m[0] * pd.m[1] * pd.m[2];
+
+    double* W = (double*)malloc(sizeof(double) * (size_t)(PN * nf));
+    /* face values of every cell (incl. one ghost layer) along the current direction */
+    double* Wm = (double*)malloc(sizeof(double) * (size_t)(PN * nf));
+    double* Wp = (double*)malloc(sizeof(double) * (size_t)(PN * nf));
+    /* fluxes at the n_d + 1 faces along the current direction, interior elsewhere */
+    int64_t nface_max = (nx + 1) * ny * nz;
+    if (dim >= 2 && nx * (ny + 1) * nz > nface_max) nface_max = nx * (ny + 1) * nz;
+    if (dim >= 3 && nx * ny * (nz + 1) > nface_max) nface_max = nx * ny * (nz + 1);
+    double* Fh = (double*)malloc(sizeof(double) * (size_t)(nface_max * nf));
+    /* accumulated flux differences, per field and cell */
+    double* acc = (double*)malloc(sizeof(double) * (size_t)(N * nf));
+    if (!W || !Wm || !Wp || !Fh || !acc) {
+        free(W); free(Wm); free(Wp); free(Fh); free(acc);
+        return OC_ENOMEM;
+    }
+
+    ghost_fill(P, &pd, U, W);
+
+    for (int d = 0; d < dim; ++d) {
+        const int64_t e[3] = { d == 0, d == 1, d == 2 };
+        const int64_t stride = (d == 0) ? 1 : (d == 1 ? pd.m[0] : pd.m[0] * pd.m[1]);
+        /* Step 2: reconstruction. Face values of every cell in the range [-1, n_d] along d
+         * (interior along the other axes). */
+        for (int f = 0; f < nf; ++f) {
+            const double* Wf = W + f * PN;
+            #pragma omp parallel for schedule(static)
+            for (int64_t k = -e[2]; k < nz + e[2]; ++k)
+                for (int64_t j = -e[1]; j < ny + e[1]; ++j)
+                    for (int64_t i = -e[0]; i < nx + e[0]; ++i) {
+                        int64_t c = pidx(&pd, i, j, k);
+                        reconstruct(P->recon, Wf[c - stride], Wf[c], Wf[c + stride],
+                                    &Wm[f * PN + c], &Wp[f * PN + c]);
+                    }
+        }
+        /* Step 3: numerical flux at every face along d. Face index (i, j, k) along d is the
+         * face between cell idx - e_d and cell idx. */
+        const int64_t fx = nx + e[0], fy = ny + e[1], fz = nz + e[2];
+        const int64_t NF = fx * fy * fz;
+        const double a_inv = inv_dx(P, d);
+        #pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < fz; ++k)
+            for (int64_t j = 0; j < fy; ++j)
+                for (int64_t i = 0; i < fx; ++i) {
+                    int64_t cR = pidx(&pd, i, j, k);
+                    int64_t cL = cR - stride;
+                    double UL[OC_MAXF], UR[OC_MAXF], F[OC_MAXF];
+                    for (int f = 0; f < nf; ++f) {
+                        UL[f] = Wp[f * PN + cL];
+                        UR[f] = Wm[f * PN + cR];
+                    }
+                    oc_numerical_flux(P, d, UL, UR, F);
+                    int64_t fi = (k * fy + j) * fx + i;
+                    for (int f = 0; f < nf; ++f) Fh[f * NF + fi] = F[f];
+                }
+        /* Step 4: flux difference along d, added in direction order x, y, z. */
+        #pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
+                for (int64_t i = 0; i < nx; ++i) {
+                    int64_t fm = (k * fy + j) * fx + i;
+                    int64_t fp = ((k + e[2]) * fy + (j + e[1])) * fx + (i + e[0]);
+                    int64_t cell = (k * ny + j) * nx + i;
+                    for (int f = 0; f < nf; ++f) {
+                        double term = (Fh[f * NF + fp] - Fh[f * NF + fm]) * a_inv;
+                        if (d == 0) acc[f * N + cell] = term;
+                        else        acc[f * N + cell] = acc[f * N + cell] + term;
+                    }
+                }
+    }
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N * nf; ++c) rhs[c] = -acc[c];
+
+    free(W); free(Wm); free(Wp); free(Fh); free(acc);
+    return OC_OK;
+}
+
+/* ---------------------------------------------------------------- wave speed / CFL */
+
+/* Maximum over cells and directions of (|u_d| + c) / dx_d for one sample, and whether any
+ * cell is non-physical (rho <= 0, p <= 0 or a non-finite component). */
+void oc_max_speed(const oc_problem* P, const double* U, double* M_out, int* bad_out)
+{
+    const int nf = oc_num_fields(P);
+    const int64_t N = cells_of(P);
+    const int dim = P->dim;
+    const double gamma = P->gamma, gm1 = P->gamma - 1.0;
+    double M = 0.0;
+    int bad = 0;
+    for (int64_t c = 0; c < N; ++c) {
+        double V[OC_MAXF];
+        for (int f = 0; f < nf; ++f) {
+            V[f] = U[f * N + c];
+            if (!isfinite(V[f])) bad = 1;
+        }
+        double m = 0.0;
+        if (P->eq == OC_EQ_EULER) {
+            oc_prim w = euler_prim(V, dim, gamma, gm1);
+            if (!(V[0] > 0.0) || !(w.p > 0.0)) bad = 1;
+            for (int d = 0; d < dim; ++d) {
+                double a = (fabs(w.u[d]) + w.c) * inv_dx(P, d);
+                m = (d == 0) ? a : dmax(m, a);
+            }
+        } else {
+            for (int d = 0; d < dim; ++d) {
+                double s = (P->eq == OC_EQ_BURGERS) ? fabs(V[0]) : fabs(P->vel[d]);
+                double a = s * inv_dx(P, d);
+                m = (d == 0) ? a : dmax(m, a);
+            }
+        }
+        if (m > M) M = m;
+    }
+    *M_out = M;
+    *bad_out = bad;
+}
+
+/* ---------------------------------------------------------------- time stepping */
+
+static int n_stages(int integrator)
+{
+    return integrator == OC_INT_FE ? 1 : (integrator == OC_INT_RK2 ? 2 : 3);
+}
+
+static double stage_beta(int integrator, int s)
+{
+    if (s == 0) return 1.0;
+    if (integrator == OC_INT_RK2) return 0.5;
+    return (s == 1) ? 0.25 : (2.0 / 3.0);
+}
+
+/* One full SSP Runge--Kutta step of size dt on one sample, in place. */
+int oc_step(const oc_problem* P, double* U, double dt)
+{
+    const int nf = oc_num_fields(P);
+    const int64_t N = cells_of(P) * nf;
+    double* Un = (double*)malloc(sizeof(double) * (size_t)N);
+    double* Us = (double*)malloc(sizeof(double) * (size_t)N);
+    double* R = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!Un || !Us || !R) { free(Un); free(Us); free(R); return OC_ENOMEM; }
+    memcpy(Un, U, sizeof(double) * (size_t)N);
+    memcpy(Us, U, sizeof(double) * (size_t)N);
+    const int S = n_stages(P->integrator);
+    int st = OC_OK;
+    for (int s = 0; s < S && st == OC_OK; ++s) {
+        st = oc_rhs(P, Us, R);
+        const double beta = stage_beta(P->integrator, s);
+        #pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < N; ++c)
+            Us[c] = Un[c] + (beta * ((Us[c] - Un[c]) + (dt * R[c])));
+    }
+    if (st == OC_OK) memcpy(U, Us, sizeof(double) * (size_t)N);
+    free(Un); free(Us); free(R);
+    return st;
+}
+
+/* Evolve each sample of U[batch][fields][cells] from t[b] to t_end with adaptive CFL
+ * steps. Per sample: steps[b] = number of steps taken, err[b] = status. The state is
+ * checked (non-physical values) before every step and at the end. */
+int oc_evolve(const oc_problem* P, double* U, int64_t batch, double* t, double t_end,
+              double cfl, int64_t max_steps, int64_t* steps, int32_t* err)
+{
+    int st = oc_validate(P);
+    if (st) return st;
+    if (!(cfl > 0.0) || cfl > 1.0 || batch < 0 || max_steps < 0) return OC_EINVAL;
+    const int nf = oc_num_fields(P);
+    const int64_t N = cells_of(P) * nf;
+    int rc = OC_OK;
+    for (int64_t b = 0; b < batch; ++b) {
+        double* Ub = U + b * N;
+        double tb = t[b];
+        int64_t k = 0;
+        int32_t e = OC_OK;
+        for (;;) {
+            double M;
+            int bad;
+            oc_max_speed(P, Ub, &M, &bad);
+            if (bad) { e = OC_ENONPHYS; break; }
+            if (!(tb < t_end)) break;
+            if (k >= max_steps) { e = OC_EMAXSTEPS; break; }
+            double dt = (M == 0.0) ? (t_end - tb) : (cfl / M);
+            int last = 0;
+            if (tb + dt >= t_end) { dt = t_end - tb; last = 1; }
+            int s2 = oc_step(P, Ub, dt);
+            if (s2) return s2;
+            tb = last ? t_end : (tb + dt);
+            k += 1;
+        }
+        t[b] = tb;
+        if (steps) steps[b] = k;
+        if (err) err[b] = e;
+        if (e != OC_OK && rc == OC_OK) rc = e;
+    }
+    return rc;
+}
+
+/* Fixed time step: nsteps steps of size dt for every sample. Fails a sample with
+ * OC_ECFL when dt * M exceeds cfl_bound before a step, OC_ENONPHYS on a bad state. */
+int oc_evolve_fixed_dt(const oc_problem* P, double* U, int64_t batch, double dt,
+                       int64_t nsteps, double cfl_bound, int32_t* err)
+{
+    int st = oc_validate(P);
+    if (st) return st;
+    if (!(dt > 0.0) || nsteps < 0 || batch < 0) return OC_EINVAL;
+    const int nf = oc_num_fields(P);
+    const int64_t N = cells_of(P) * nf;
+    int rc = OC_OK;
+    for (int64_t b = 0; b < batch; ++b) {
+        double* Ub = U + b * N;
+        int32_t e = OC_OK;
+        for (int64_t k = 0; k <= nsteps; ++k) {
+            double M;
+            int bad;
+            oc_max_speed(P, Ub, &M, &bad);
+            if (bad) { e = OC_ENONPHYS; break; }
+            if (k == nsteps) break;
+            if (dt * M > cfl_bound) { e = OC_ECFL; break; }
+            int s2 = oc_step(P, Ub, dt);
+            if (s2) return s2;
+        }
+        if (err) err[b] = e;
+        if (e != OC_OK && rc == OC_OK) rc = e;
+    }
+    return rc;
+}
+
+/* ---------------------------------------------------------------- statistics */
+
+/* Number of statistical quantities: Euler (rho, u_1..u_d, E), scalar (u). */
+int oc_num_quantities(const oc_problem* P)
+{
+    return oc_num_fields(P);
+}
+
+/* q[quantity][cells] of one sample: rho, u_k = m_k * (1/rho), E; or the scalar itself. */
+void oc_quantities(const oc_problem* P, const double* U, double* q)
+{
+    const int nf = oc_num_fields(P);
+    const int64_t N = cells_of(P);
+    if (P->eq != OC_EQ_EULER) {
+        memcpy(q, U, sizeof(double) * (size_t)N);
+        return;
+    }
+    for (int64_t c = 0; c < N; ++c) {
+        double ir = 1.0 / U[c];
+        q[c] = U[c];
+        for (int k = 0; k < P->dim; ++k) q[(1 + k) * N + c] = U[(1 + k) * N + c] * ir;
+        q[(nf - 1) * N + c] = U[(nf - 1) * N + c];
+    }
+}
+
+/* Second-order structure function of one periodic field q[cells] at lag h (cells):
+ * S(h) = (1 / (d N)) sum_{axes e} sum_x (q(x + h e) - q(x))^2, summed axis by axis in
+ * row-major cell order. */
+double oc_structure_function(const oc_problem* P, const double* q, int64_t h)
+{
+    const int64_t nx = P->n[0], ny = P->n[1], nz = P->n[2];
+    double s = 0.0;
+    for (int d = 0; d < P->dim; ++d) {
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
+                for (int64_t i = 0; i < nx; ++i) {
+                    int64_t i2 = (d == 0) ? (i + h) % nx : i;
+                    int64_t j2 = (d == 1) ? (j + h) % ny : j;
+                    int64_t k2 = (d == 2) ? (k + h) % nz : k;
+                    double diff = q[(k2 * ny + j2) * nx + i2] - q[(k * ny + j) * nx + i];
+                    s = s + (diff * diff);
+                }
+    }
+    return s / ((double)P->dim * (double)cells_of(P));
+}
+
+/* Welford's update of running mean and M2 with one more observation x (n = new count). */
+static void welford(double x, int64_t n, double* mean, double* m2)
+{
+    double delta = x - *mean;
+    *mean = *mean + (delta / (double)n);
+    *m2 = *m2 + (delta * (x - *mean));
+}
+
+/* Add the samples U[batch] in index order to the running statistics:
+ *   mean[q][cells], m2[q][cells]    per-cell moments of the quantities;
+ *   s2mean[q][max_h], s2m2[q][max_h] moments over samples of S_q(h), h = 1..max_h;
+ *   *count                          number of samples seen so far (updated). */
+int oc_stats_accumulate(const oc_problem* P, const double* U, int64_t batch, int32_t max_h,
+                        double* mean, double* m2, double* s2mean, double* s2m2, int64_t* count)
+{
+    int st = oc_validate(P);
+    if (st) return st;
+    if (max_h > 0) {
+        for (int k = 0; k < P->dim; ++k)
+            if (P->bc[k] != OC_BC_PERIODIC || max_h >= P->n[k]) return OC_ENOTSUP;
+    }
+    const int nf = oc_num_fields(P);
+    const int nq = oc_num_quantities(P);
+    const int64_t N = cells_of(P);
+    double* q = (double*)malloc(sizeof(double) * (size_t)(N * nq));
+    if (!q) return OC_ENOMEM;
+    for (int64_t b = 0; b < batch; ++b) {
+        oc_quantities(P, U + b * N * nf, q);
+        int64_t n = *count + 1;
+        #pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < N * nq; ++c) welford(q[c], n, &mean[c], &m2[c]);
+        for (int qi = 0; qi < nq; ++qi)
+            for (int32_t h = 1; h <= max_h; ++h) {
+                double s = oc_structure_function(P, q + qi * N, h);
+                welford(s, n, &s2mean[qi * max_h + (h - 1)], &s2m2[qi * max_h + (h - 1)]);
+            }
+        *count = n;
+    }
+    free(q);
+    return OC_OK;
+}
+
+/* ---------------------------------------------------------------- misc */
+
+int oc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
