@@ -1,0 +1,200 @@
+"""Benchmark of the finite-volume hot path on one MI355X.
+
+Default workload: 2D compressible Euler, Kelvin--Helmholtz shear layer on the periodic unit
+square at 1024^2 cells, FP64, WENO3 reconstruction, HLLC flux, SSP-RK3, CFL 0.4 (seed 1912,
+sample 0). One "step" is one full time step of the whole path: the CFL wave-speed reduction,
+three fused Runge--Kutta stage launches (ghost fill, reconstruction, flux, divergence, stage
+combination) and the device-side step control.
+
+Prints ONE JSON line: cell-updates/s (cells x steps / wall time of the timed region, the
+state already resident in HBM), the roofline of the dominant kernel (the stage kernel,
+timed with HIP events on the library's stream over its own launches) and the CPU oracle's
+rate on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh3d|mc|sod]
+    python bench.py --copy-calibration     # plain copy of known size, for rocprof counters
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, 8 TB/s
+FP64_VALU_TFLOPS = 78.6     # MI355X FP64 vector (FMA = 2 flops)
+
+# Algorithmic HBM bytes per cell per full step (streaming minimum: each stage reads its
+# input state once, stages >= 2 re-read U^n, every stage writes its output once; halos and
+# faces never leave the chip).
+def algorithmic_bytes_per_cell_step(nf: int, integrator: str) -> int:
+    per = 8 * nf
+    if integrator == "forward_euler":
+        return 2 * per
+    if integrator == "ssprk2":
+        return 2 * per + 3 * per
+    return 2 * per + 3 * per + 3 * per
+
+
+WORKLOADS = {
+    "kh2d": dict(name="kh2d_1024x1024_weno3_hllc_ssprk3", dim=2, n=1024, flux="hllc",
+                 recon="weno3", integrator="ssprk3", cfl=0.4, batch=1, seed=1912,
+                 steps=2000, warmup=100, cpu_steps=8),
+    "kh3d": dict(name="kh3d_512^3_weno3_hllc_ssprk3", dim=3, n=512, flux="hllc",
+                 recon="weno3", integrator="ssprk3", cfl=0.4, batch=1, seed=1914,
+                 steps=20, warmup=2, cpu_steps=1),
+    "mc": dict(name="kh2d_256x256_x1024_samples_weno3_hllc_ssprk3", dim=2, n=256, flux="hllc",
+               recon="weno3", integrator="ssprk3", cfl=0.4, batch=1024, seed=1912,
+               steps=50, warmup=5, cpu_steps=2),
+    "sod": dict(name="sod_1024_first_order_rusanov_forward_euler", dim=1, n=1024,
+                flux="rusanov", recon="first_order", integrator="forward_euler", cfl=0.45,
+                batch=1, seed=0, steps=1000, warmup=100, cpu_steps=1000),
+}
+
+
+def initial_state(w):
+    import numpy as np
+    import fv_inputs as fi
+    if w["dim"] == 1:
+        return fi.sod_state(w["n"])
+    if w["dim"] == 2:
+        c, phi = fi.kh_coefficients(w["seed"], np.arange(w["batch"]))
+        return fi.kh2d_state(w["n"], c, phi)
+    cx, px, cz, pz = fi.kh3d_coefficients(w["seed"], np.arange(w["batch"]))
+    return fi.kh3d_state(w["n"], cx, px, cz, pz)
+
+
+def cpu_baseline(w, U0, steps):
+    """The oracle as it stands, on the host's cores, over a bounded prefix of the run."""
+    import oracle as O
+    cores = O.set_threads(0)
+    p = O.Problem(dim=w["dim"], n=(w["n"],) * w["dim"], eq="euler", flux=w["flux"],
+                  recon=w["recon"], integrator=w["integrator"],
+                  bc=("transmissive",) if w["dim"] == 1 else ("periodic",) * 3)
+    samples = min(U0.shape[0], 2)
+    U = U0[:samples]
+    t0 = time.perf_counter()
+    _, _, k, _ = O.evolve(p, U, 1e9, w["cfl"], max_steps=steps)
+    el = time.perf_counter() - t0
+    cells = w["n"] ** w["dim"]
+    return {"value": cells * int(k.sum()) / el, "unit": "cell-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {steps} steps of {samples} sample(s) of the same workload "
+                      f"({cells} cells each), {el:.1f} s"}
+
+
+def copy_calibration():
+    """A plain device copy of 1 GiB, ten times (for FETCH_SIZE / WRITE_SIZE scaling)."""
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 10}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="kh2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true")
+    a = ap.parse_args()
+
+    ws = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or ws != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each GPU would hold its own periodic subdomain; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    if a.copy_calibration:
+        copy_calibration()
+        return
+
+    import numpy as np
+    import torch
+    from paper_1912_07645_amd import Solver, fv
+
+    w = dict(WORKLOADS[a.workload])
+    K = a.steps if a.steps is not None else w["steps"]
+    W = a.warmup if a.warmup is not None else w["warmup"]
+    dev = torch.device("cuda:0")
+    U0 = initial_state(w)
+    bc = "transmissive" if w["dim"] == 1 else "periodic"
+    s = Solver(dim=w["dim"], n=(w["n"],) * w["dim"], eq="euler", flux=w["flux"],
+               recon=w["recon"], integrator=w["integrator"], bc=bc, device=dev)
+    U = torch.from_numpy(U0).to(dev)
+    B = U.shape[0]
+    t = torch.zeros(B, dtype=torch.float64, device=dev)
+    steps_t = torch.zeros(B, dtype=torch.int64, device=dev)
+    err = torch.zeros(B, dtype=torch.int32, device=dev)
+    tuned = s.tune(U, reps=3) if s.num_variants() > 1 else 0
+    tile, _ = s.tile()
+
+    t_end = 1e9
+    s.advance(U, t, t_end, w["cfl"], W, steps_t, err)
+    torch.cuda.synchronize()
+    # timed region: K full steps, state resident in HBM
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.advance(U, t, t_end, w["cfl"], K, steps_t, err)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert st == 0 and int(steps_t.min()) == K, (st, steps_t.min())
+    cells = w["n"] ** w["dim"]
+    value = cells * B * K / el
+
+    # stage-kernel timing with HIP events on the library's stream, over K more steps
+    fv.fv_profile_enable(s.handle, True)
+    s.advance(U, t, t_end, w["cfl"], K, steps_t, err)
+    torch.cuda.synchronize()
+    stage_ms, launches = fv.fv_profile_read(s.handle)
+    fv.fv_profile_enable(s.handle, False)
+    nstages = {"forward_euler": 1, "ssprk2": 2, "ssprk3": 3}[w["integrator"]]
+    assert launches == K * nstages, (launches, K, nstages)
+    nf = w["dim"] + 2
+    bytes_step = algorithmic_bytes_per_cell_step(nf, w["integrator"]) * cells * B
+    avg_launch_s = stage_ms * 1e-3 / launches
+    bytes_per_launch = bytes_step / nstages
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+
+    out = {
+        "metric": "FP64 cell-updates/s",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": el / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "grid": [w["n"]] * w["dim"], "samples": B,
+                   "cells_per_sample": cells, "cfl": w["cfl"], "seed": w["seed"],
+                   "tile": list(tile), "tuned_variant": tuned},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage_kernel", "avg_launch_us": avg_launch_s * 1e6,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "hbm_frac_whole_step": bytes_step * K / el / 1e9 / HBM_PEAK_GBS,
+    }
+    if w["name"].startswith("kh2d_256x256_x1024"):
+        out["mc_samples_steps_per_s"] = B * K / el
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, U0, w["cpu_steps"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

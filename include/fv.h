@@ -1,0 +1,221 @@
+/*
+ * fv.h -- C ABI of libfv, an MI355X (gfx950) library for the explicit finite-volume
+ * method of Lye, "Alsvinn: A fast multi-GPGPU finite volume solver with a strong emphasis on
+ * reproducibility" (arXiv:1912.07645), and its on-device Monte Carlo statistics.
+ *
+ * The method (Section 2.1): solve u_t + div F(u) = 0 on D x [0, T], u(x, 0) = u_0 (eq. 1.1)
+ * through the semi-discrete scheme d/dt U_i + sum_k (F_{i+1/2 e_k} - F_{i-1/2 e_k}) / dx_k
+ * = 0 (eq. 2.1), with a numerical flux (Rusanov, HLL, HLLC), a reconstruction of the face
+ * values (piecewise constant, MUSCL with the minmod limiter, third-order WENO) and a strong
+ * stability preserving Runge--Kutta stepper. Section 2.2: Monte Carlo estimates
+ * (1/M) sum_k G(u_k) over samples, with per-cell mean and variance and two-point structure
+ * functions computed on the GPU.
+ *
+ * Conventions shared by every entry point:
+ *   - All floating-point data is IEEE binary64.
+ *   - State arrays are device memory in structure-of-arrays layout
+ *     [batch][field][nz][ny][nx], x fastest, densely packed (unused axes have extent 1).
+ *     Euler fields are (rho, m_x[, m_y[, m_z]], E); scalar equations have one field.
+ *   - Device arrays passed in are owned by the caller and must stay valid until the call
+ *     returns. The library owns only its opaque handles and any workspace it allocates
+ *     itself; it never frees caller memory.
+ *   - Work is ordered on the solver's stream (fv_set_stream). Calls that poll device flags
+ *     (fv_evolve, fv_advance, fv_evolve_fixed_dt) return after the device has finished.
+ *   - Every function returns fv_status (or a plain value where stated). On failure a
+ *     description is available from fv_last_error() in the calling thread. Argument errors
+ *     are found on the host before any device work is enqueued. No C++ exception crosses the
+ *     boundary.
+ *   - Results are bit-for-bit reproducible from run to run and independent of the batch
+ *     size, the number of samples per launch and the tile shape chosen by the tuner.
+ */
+#ifndef FV_H
+#define FV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FV_OK = 0,
+    FV_EINVAL = 1,      /* bad argument: null pointer, size <= 0, cfl outside (0, 1], ...   */
+    FV_ENOTSUP = 2,     /* valid but unsupported combination (HLLC for a scalar equation)   */
+    FV_ENOMEM = 3,      /* device or host allocation failed, or workspace too small         */
+    FV_EDEVICE = 4,     /* a HIP runtime call failed                                        */
+    FV_ENONPHYS = 5,    /* a sample reached rho <= 0, p <= 0 or a non-finite value          */
+    FV_EMAXSTEPS = 6,   /* a sample did not reach t_end within max_steps steps              */
+    FV_ECFL = 7         /* fixed-dt run: dt * max wave speed / dx exceeded the bound        */
+} fv_status;
+
+typedef enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1 } fv_bc;
+typedef enum { FV_EQ_ADVECTION = 0, FV_EQ_BURGERS = 1, FV_EQ_EULER = 2 } fv_eq_kind;
+typedef enum { FV_FLUX_RUSANOV = 0, FV_FLUX_HLL = 1, FV_FLUX_HLLC = 2 } fv_flux;
+typedef enum { FV_RECON_FIRST_ORDER = 0, FV_RECON_MUSCL_MINMOD = 1, FV_RECON_WENO3 = 2 } fv_recon;
+typedef enum { FV_INT_FORWARD_EULER = 0, FV_INT_SSPRK2 = 1, FV_INT_SSPRK3 = 2 } fv_integrator;
+
+/* Uniform Cartesian grid on [lo, hi] per axis (Section 2.1: cells i with averages U_i).
+ * dim in 1..3; n[k] >= 1 cells on axis k, and n[k] == 1 for k >= dim; bc[k] is the
+ * boundary condition on both ends of axis k (periodic wrap, or transmissive: every ghost
+ * layer copies the edge cell). */
+typedef struct {
+    int32_t dim;
+    int32_t bc[3];
+    int64_t n[3];
+    double lo[3];
+    double hi[3];
+} fv_grid;
+
+/* The flux function F of eq. (1.1): linear advection F = a u (velocity[k] = a_k), Burgers
+ * F = u^2/2 in every direction, or the compressible Euler equations with the gamma law
+ * p = (gamma - 1)(E - |m|^2 / (2 rho)) (gamma > 1). */
+typedef struct {
+    int32_t kind;          /* fv_eq_kind */
+    double gamma;
+    double velocity[3];
+} fv_equation;
+
+typedef struct fv_solver fv_solver;   /* opaque, library-owned */
+typedef struct fv_stats fv_stats;     /* opaque, library-owned */
+
+/* ------------------------------------------------------------------ solver lifetime */
+
+/* Create a solver for one grid, equation and scheme (Section 2.1: numerical flux, face
+ * reconstruction, SSP Runge--Kutta stepper). flux, recon, integrator take the enum values
+ * above. *out receives the handle. FV_ENOTSUP for HLLC with a scalar equation; FV_EINVAL
+ * for any malformed grid or enum; FV_EDEVICE if no gfx950 device is current. */
+fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32_t flux, int32_t recon,
+                    int32_t integrator, fv_solver** out);
+
+/* Destroy a solver and the workspace it allocated itself. NULL is accepted. */
+fv_status fv_destroy(fv_solver* solver);
+
+/* Order the solver's device work after, and before, work on this HIP stream (hipStream_t
+ * passed as void*; NULL means the null stream). Default: the null stream. */
+fv_status fv_set_stream(fv_solver* solver, void* hip_stream);
+
+/* Number of conserved fields: dim + 2 for Euler, 1 for scalar equations; -1 on NULL. */
+int32_t fv_num_fields(const fv_solver* solver);
+
+/* Bytes of device workspace that fv_evolve / fv_advance / fv_evolve_fixed_dt need for a
+ * batch of `batch` samples (Runge--Kutta stage copies and per-sample control words). */
+fv_status fv_workspace_size(const fv_solver* solver, int64_t batch, size_t* bytes);
+
+/* Hand the solver caller-owned device memory (256-byte aligned) to use as workspace
+ * instead of allocating its own. dev_ptr = NULL returns to library-allocated workspace.
+ * A later call whose batch needs more than `bytes` fails with FV_ENOMEM. */
+fv_status fv_set_workspace(fv_solver* solver, void* dev_ptr, size_t bytes);
+
+/* ------------------------------------------------------------------ time stepping */
+
+/* Evolve each sample b of state (device double[batch][fields][cells], updated in place)
+ * from t[b] to t_end (device double[batch], in/out) with explicit SSP Runge--Kutta steps of
+ * eq. (2.1). Each step of sample b uses dt_b = cfl / M_b, with M_b = max over cells and axes
+ * of (|u_k| + c) / dx_k (Euler), |u| / dx_k (Burgers), |a_k| / dx_k (advection), evaluated
+ * on the state the step starts from; the last step is clipped to end exactly at t_end.
+ * Samples advance independently (per-sample dt). Before every step, and at the end, the
+ * state is checked: rho <= 0, p <= 0 or a non-finite value stops that sample with
+ * FV_ENONPHYS. A sample that needs more than max_steps steps stops with FV_EMAXSTEPS.
+ * steps (device int64[batch], may be NULL) receives the number of steps taken; err
+ * (device int32[batch], may be NULL) the per-sample status. Returns FV_OK if every sample
+ * reached t_end, otherwise the first failing sample's status. cfl must lie in (0, 1]. */
+fv_status fv_evolve(fv_solver* solver, double* state, int64_t batch, double* t, double t_end,
+                    double cfl, int64_t max_steps, int64_t* steps, int32_t* err);
+
+/* As fv_evolve, but take at most nsteps steps per sample and treat stopping early as
+ * success: a sample that has not reached t_end after nsteps steps keeps err = FV_OK. */
+fv_status fv_advance(fv_solver* solver, double* state, int64_t batch, double* t, double t_end,
+                     double cfl, int64_t nsteps, int64_t* steps, int32_t* err);
+
+/* Exactly nsteps steps of the fixed size dt for every sample (no clipping). Before each
+ * step a sample whose dt * M_b exceeds cfl_bound stops with FV_ECFL; non-physical states
+ * stop it with FV_ENONPHYS. err as in fv_evolve. */
+fv_status fv_evolve_fixed_dt(fv_solver* solver, double* state, int64_t batch, double dt,
+                             int64_t nsteps, double cfl_bound, int32_t* err);
+
+/* Several solvers (grids of different resolution sharing one equation and scheme, e.g. the
+ * levels of a multilevel Monte Carlo estimate, Section 2.2) evolved together: every
+ * Runge--Kutta stage of all groups runs as one launch. Group g has solvers[g], its batch
+ * states[g][batches[g]][fields][cells], times t[g] (device double[batches[g]]) and err[g]
+ * (device int32[batches[g]], entries may be NULL). All solvers must share equation, flux,
+ * reconstruction, integrator and dimension; their stream is that of solvers[0]. Semantics
+ * per sample as in fv_evolve. */
+fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers, double* const* states,
+                          const int64_t* batches, double* const* t, double t_end, double cfl,
+                          int64_t max_steps, int32_t* const* err);
+
+/* ------------------------------------------------------------------ tile tuning */
+
+/* Tile shapes: each (dimension, equation, reconstruction, flux) has one or more compiled
+ * tile shapes ("variants"), all producing bit-identical results. fv_num_variants returns
+ * their number (-1 on NULL); fv_set_variant selects one (FV_EINVAL if out of range);
+ * fv_get_tile reports the current tile shape in cells and its variant index (any output
+ * may be NULL). */
+int32_t fv_num_variants(const fv_solver* solver);
+fv_status fv_set_variant(fv_solver* solver, int32_t variant);
+fv_status fv_get_tile(const fv_solver* solver, int32_t* bx, int32_t* by, int32_t* bz,
+                      int32_t* variant);
+
+/* Autotuner: time a few full steps of every variant on a copy of `state` (device,
+ * [batch][fields][cells], not modified) and select the fastest; *chosen (may be NULL)
+ * receives it. reps < 1 means 3 timed repetitions per variant. */
+fv_status fv_tune(fv_solver* solver, double* state, int64_t batch, int32_t reps,
+                  int32_t* chosen);
+
+/* ------------------------------------------------------------------ kernel timing */
+
+/* Kernel timing for roofline measurements. While enabled (on != 0), the time-stepping
+ * calls enqueue their launches directly instead of replaying a graph, and bracket every
+ * Runge--Kutta stage launch with HIP events on the solver's internal stream; enabling or
+ * disabling resets the totals. fv_profile_read returns the accumulated device time of the
+ * stage launches in milliseconds and their number (outputs may be NULL). Launches of
+ * samples that had already finished count as well (they return immediately). */
+fv_status fv_profile_enable(fv_solver* solver, int32_t on);
+fv_status fv_profile_read(const fv_solver* solver, double* stage_ms, int64_t* stage_launches);
+
+/* ------------------------------------------------------------------ statistics */
+
+/* Running Monte Carlo statistics (Section 2.2) on the solver's grid. Quantities: Euler
+ * (rho, u_1..u_dim, E) with u_k = m_k * (1/rho); scalar equations the field itself.
+ * max_h >= 0 is the largest lag of the second-order structure function
+ * S_q(h) = 1/(dim N) sum_axes sum_x (q(x + h e_axis) - q(x))^2 (periodic grids only,
+ * max_h < n[k] on every axis; FV_ENOTSUP otherwise). */
+fv_status fv_stats_create(const fv_solver* solver, int32_t max_h, fv_stats** out);
+
+/* Add the samples of state (device double[batch][fields][cells]) in index order:
+ * per-cell Welford updates of the mean and M2 of every quantity, and Welford updates over
+ * samples of S_q(h), h = 1..max_h. Stream-ordered on the solver's stream. */
+fv_status fv_stats_accumulate(fv_stats* stats, const double* state, int64_t batch);
+
+/* Copy the statistics into caller device memory (any pointer may be NULL):
+ * mean, var: double[quantities][cells] (var = M2 / count, population variance);
+ * s2_mean, s2_var: double[quantities][max_h]; count: host int64. Synchronises. */
+fv_status fv_stats_read(const fv_stats* stats, double* mean, double* var, double* s2_mean,
+                        double* s2_var, int64_t* count);
+
+/* Reset to zero samples. */
+fv_status fv_stats_reset(fv_stats* stats);
+
+fv_status fv_stats_destroy(fv_stats* stats);
+
+/* ------------------------------------------------------------------ misc */
+
+/* Human-readable description of the last failure in this thread ("" if none). Valid until
+ * the next fv_* call in the same thread. */
+const char* fv_last_error(void);
+
+/* Arithmetic self-check: quot[i] = a[i] / b[i], root[i] = sqrt(a[i]) on the device with the
+ * same division and square root the kernels use (all device arrays of n doubles), so that
+ * tests can compare them bit for bit with correctly rounded host results. Synchronises. */
+fv_status fv_check_arith(const double* a, const double* b, double* quot, double* root,
+                         int64_t n);
+
+/* Library version string. */
+const char* fv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FV_H */

@@ -1,0 +1,296 @@
+// fv_stage.h -- the fused Runge--Kutta stage kernel of the finite-volume scheme and the
+// wave-speed reduction kernel, as templates over (dimension, equation, reconstruction,
+// numerical flux, tile shape, workgroup size).
+//
+// One workgroup of NT threads updates one tile of BX x BY x BZ cells of one sample:
+//   1. ghost fill + load: the tile and a halo of G cells on every active axis are read from
+//      HBM into LDS; periodic axes wrap, transmissive axes clamp to the edge cell, so no
+//      padded copy exists in memory;
+//   2. faces: every face of the tile, of every axis, is reconstructed and its numerical flux
+//      computed exactly once. The faces of all axes form one list (x faces, then y, then z),
+//      dealt to the threads in order, with the face axis a run-time value; tile shapes are
+//      chosen so the list fills the workgroup's wavefronts evenly (e.g. 16 x 15 cells have
+//      511 faces for 2 x 256 lanes), so no wavefront does an extra pass for the "+1" row of
+//      faces that every tile has along each axis;
+//   3. divergence: each cell adds (F_+ - F_-) / dx_k in the order x, y, z (eq. 2.1);
+//   4. Runge--Kutta stage: U^(s) = U^n + beta ((U^(s-1) - U^n) + dt L(U^(s-1))), written to
+//      HBM; in the last stage the new state's wave speed is reduced across the workgroup
+//      (wavefront shuffles, then LDS) and merged into the sample's maximum with an atomic max
+//      on the bit pattern (exact and order-independent), and non-physical cells are flagged.
+#pragma once
+
+#include "fv_physics.h"
+
+namespace fvk {
+
+template <int RECON>
+struct Ghost {
+    static constexpr int value = (RECON == REC_FIRST) ? 1 : 2;
+};
+
+__device__ __forceinline__ int32_t wrap_index(int32_t i, int32_t n, int32_t bc)
+{
+    if (bc == BC_PERIODIC) {
+        int32_t r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; remap so that each XCD receives a
+// contiguous range of tiles and halo re-reads of neighbouring tiles hit its own L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks)
+{
+    const int64_t full = (nblocks / 8) * 8;
+    if (b >= full) return b;
+    return (b % 8) * (full / 8) + (b / 8);
+}
+
+template <int DIM, int EQ, int RECON, int BX, int BY, int BZ, int NT>
+struct StageTile {
+    static constexpr int NF = NumFields<DIM, EQ>::value;
+    static constexpr int G = Ghost<RECON>::value;
+    static constexpr int PX = BX + 2 * G;
+    static constexpr int PY = (DIM >= 2) ? BY + 2 * G : 1;
+    static constexpr int PZ = (DIM >= 3) ? BZ + 2 * G : 1;
+    static constexpr int PCELLS = PX * PY * PZ;
+    static constexpr int CELLS = BX * BY * BZ;
+    static constexpr int CPT = (CELLS + NT - 1) / NT;   // cells per thread
+    static constexpr int NFX = (BX + 1) * BY * BZ;       // faces normal to x
+    static constexpr int NFY = (DIM >= 2) ? BX * (BY + 1) * BZ : 0;
+    static constexpr int NFZ = (DIM >= 3) ? BX * BY * (BZ + 1) : 0;
+    static constexpr int NFACES = NFX + NFY + NFZ;
+    static_assert(NT % 64 == 0, "whole wavefronts");
+    static_assert(DIM >= 2 || (BY == 1 && BZ == 1), "1D tiles are rows");
+    static_assert(DIM >= 3 || BZ == 1, "2D tiles are flat");
+};
+
+// All faces of the tile into sf[q][face] (x faces, then y faces, then z faces).
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
+__device__ __forceinline__ void tile_faces(const double* su, double* sf, const Phys& ph)
+{
+    using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    constexpr int NF = T::NF, G = T::G, PX = T::PX, PY = T::PY, PCELLS = T::PCELLS;
+    constexpr int NFX = T::NFX, NFY = T::NFY, NFACES = T::NFACES;
+    constexpr int GY = (DIM >= 2) ? G : 0, GZ = (DIM >= 3) ? G : 0;
+    for (int f = threadIdx.x; f < NFACES; f += NT) {
+        // decode (axis, face coordinates); each branch divides by compile-time constants
+        int nd, fx, fy, fz;
+        if (f < NFX) {
+            nd = 0;
+            fx = f % (BX + 1);
+            fy = (f / (BX + 1)) % BY;
+            fz = f / ((BX + 1) * BY);
+        } else if (DIM >= 2 && f < NFX + NFY) {
+            const int l = f - NFX;
+            nd = 1;
+            fx = l % BX;
+            fy = (l / BX) % (BY + 1);
+            fz = l / (BX * (BY + 1));
+        } else {
+            const int l = f - NFX - NFY;
+            nd = 2;
+            fx = l % BX;
+            fy = (l / BX) % BY;
+            fz = l / (BX * BY);
+        }
+        // LDS index of the cell on the right of the face (the face is its "minus" side)
+        const int c = ((fz + GZ) * PY + (fy + GY)) * PX + (fx + G);
+        const int stride = (nd == 0) ? 1 : ((nd == 1) ? PX : PX * PY);
+        double UL[NF], UR[NF], F[NF];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const double* s = su + q * PCELLS + c;
+            if (RECON == REC_FIRST) {
+                reconstruct<RECON>(0.0, s[-stride], s[0], 0.0, UL[q], UR[q]);
+            } else {
+                reconstruct<RECON>(s[-2 * stride], s[-stride], s[0], s[stride], UL[q], UR[q]);
+            }
+        }
+        numflux<DIM, EQ, FLUX>(UL, UR, nd, F, ph);
+#pragma unroll
+        for (int q = 0; q < NF; ++q) sf[q * NFACES + f] = F[q];
+    }
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = vmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Reduce (m, bad) across the workgroup and merge into the sample's words.
+template <int NT>
+__device__ __forceinline__ void block_merge_speed(double m, bool bad, unsigned long long* mbits,
+                                                  int32_t* badflag)
+{
+    __shared__ double red[NT / 64];
+    __shared__ int redbad;
+    if (threadIdx.x == 0) redbad = 0;
+    __syncthreads();
+    m = wave_max(m);
+    if (bad) atomicOr(&redbad, 1);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) r = vmax(r, red[w]);
+        atomicMax(mbits, (unsigned long long)__double_as_longlong(r));
+        if (redbad) atomicOr(badflag, 1);
+    }
+}
+
+__device__ __forceinline__ int find_group(const Group* g, int ngroups, int64_t block)
+{
+    int gi = 0;
+#pragma unroll
+    for (int i = 1; i < kMaxGroups; ++i)
+        if (i < ngroups && block >= g[i].block0) gi = i;
+    return gi;
+}
+
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
+__global__ void __launch_bounds__(NT)
+stage_kernel(const StageArgs args)
+{
+    using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    constexpr int NF = T::NF, G = T::G, PX = T::PX, PY = T::PY;
+    constexpr int PCELLS = T::PCELLS, CPT = T::CPT, CELLS = T::CELLS;
+    constexpr int NFX = T::NFX, NFY = T::NFY, NFACES = T::NFACES;
+    constexpr int GY = (DIM >= 2) ? G : 0, GZ = (DIM >= 3) ? G : 0;
+    __shared__ double su[NF * PCELLS];
+    __shared__ double sf[NF * NFACES];
+
+    const int64_t blk = xcd_remap(blockIdx.x, args.nblocks);
+    const int gi = find_group(args.g, args.ngroups, blk);
+    const Group& g = args.g[gi];
+    const int64_t local = blk - g.block0;
+    const int32_t sample = (int32_t)(local / g.ntiles);
+    const int32_t tile = (int32_t)(local % g.ntiles);
+    if (!g.active[sample]) return;   // uniform across the workgroup
+
+    const int32_t tx = tile % g.tiles[0];
+    const int32_t ty = (tile / g.tiles[0]) % g.tiles[1];
+    const int32_t tz = tile / (g.tiles[0] * g.tiles[1]);
+    const int32_t x0 = tx * BX, y0 = ty * BY, z0 = tz * BZ;
+    const int32_t nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int64_t sbase = (int64_t)sample * NF * g.cells;
+    const double* src = g.src + sbase;
+
+    // 1. ghost fill + load of the haloed tile into LDS
+    for (int e = threadIdx.x; e < PCELLS; e += NT) {
+        const int px = e % PX;
+        const int py = (e / PX) % PY;
+        const int pz = e / (PX * PY);
+        const int32_t gx = wrap_index(x0 + px - G, nx, args.bc[0]);
+        const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - G, ny, args.bc[1]) : 0;
+        const int32_t gz = (DIM >= 3) ? wrap_index(z0 + pz - G, nz, args.bc[2]) : 0;
+        const int64_t gidx = ((int64_t)gz * ny + gy) * nx + gx;
+#pragma unroll
+        for (int q = 0; q < NF; ++q) su[q * PCELLS + e] = src[q * g.cells + gidx];
+    }
+    __syncthreads();
+
+    // 2. every face of the tile, once
+    tile_faces<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT>(su, sf, g.ph);
+    __syncthreads();
+
+    // 3 + 4. divergence and Runge--Kutta stage combination
+    const double dt = g.dt[sample];
+    const double beta = args.beta;
+    double m = 0.0;
+    bool bad = false;
+    double* dst = g.dst + sbase;
+    const double* un = g.un + sbase;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        const int c = threadIdx.x + k * NT;
+        if (c >= CELLS) break;
+        const int cx = c % BX;
+        const int cy = (c / BX) % BY;
+        const int cz = c / (BX * BY);
+        const int32_t gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+        if (gx >= nx || gy >= ny || gz >= nz) continue;
+        const int64_t gidx = ((int64_t)gz * ny + gy) * nx + gx;
+        const int lc = ((cz + GZ) * PY + (cy + GY)) * PX + (cx + G);
+        const int fxm = (cz * BY + cy) * (BX + 1) + cx;
+        const int fym = NFX + (cz * (BY + 1) + cy) * BX + cx;
+        const int fzm = NFX + NFY + (cz * BY + cy) * BX + cx;
+        double out[NF];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const double* F = sf + q * NFACES;
+            double acc = (F[fxm + 1] - F[fxm]) * g.ph.inv_dx[0];
+            if (DIM >= 2) acc = acc + ((F[fym + BX] - F[fym]) * g.ph.inv_dx[1]);
+            if (DIM >= 3) acc = acc + ((F[fzm + BX * BY] - F[fzm]) * g.ph.inv_dx[2]);
+            const double rhs = -acc;
+            const double up = su[q * PCELLS + lc];
+            const double u0 = args.use_un ? un[q * g.cells + gidx] : up;
+            out[q] = u0 + (beta * ((up - u0) + (dt * rhs)));
+            dst[q * g.cells + gidx] = out[q];
+        }
+        if (args.last) {
+            bool b;
+            const double s = cell_speed<DIM, EQ>(out, g.ph, b);
+            m = vmax(m, s);
+            bad = bad || b;
+        }
+    }
+    if (args.last) block_merge_speed<NT>(m, bad, &g.mbits[sample], &g.bad[sample]);
+}
+
+// Wave speed and physicality of a state, without update (the step-0 reduction).
+template <int DIM, int EQ>
+__global__ void __launch_bounds__(kThreads)
+speed_kernel(const SpeedArgs args, int cells_per_block)
+{
+    constexpr int NF = NumFields<DIM, EQ>::value;
+    const int64_t blk = blockIdx.x;
+    const int gi = find_group(args.g, args.ngroups, blk);
+    const Group& g = args.g[gi];
+    const int64_t local = blk - g.block0;
+    const int64_t per_sample = (g.cells + cells_per_block - 1) / cells_per_block;
+    const int32_t sample = (int32_t)(local / per_sample);
+    const int64_t c0 = (local % per_sample) * cells_per_block;
+    if (!g.active[sample]) return;
+    const double* src = g.src + (int64_t)sample * NF * g.cells;
+    double m = 0.0;
+    bool bad = false;
+    for (int64_t c = c0 + threadIdx.x; c < c0 + cells_per_block && c < g.cells; c += kThreads) {
+        double U[NF];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) U[q] = src[q * g.cells + c];
+        bool b;
+        const double s = cell_speed<DIM, EQ>(U, g.ph, b);
+        m = vmax(m, s);
+        bad = bad || b;
+    }
+    block_merge_speed<kThreads>(m, bad, &g.mbits[sample], &g.bad[sample]);
+}
+
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
+void launch_stage(const StageArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((stage_kernel<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT>),
+                       dim3((unsigned)a.nblocks), dim3(NT), 0, s, a);
+}
+
+constexpr int kSpeedCellsPerBlock = 4096;
+
+template <int DIM, int EQ>
+void launch_speed(const SpeedArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((speed_kernel<DIM, EQ>), dim3((unsigned)a.nblocks), dim3(kThreads), 0, s, a,
+                       kSpeedCellsPerBlock);
+}
+
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
+constexpr StageKernel make_stage_kernel()
+{
+    return StageKernel{&launch_stage<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT>, &launch_speed<DIM, EQ>,
+                       BX, BY, BZ, kSpeedCellsPerBlock};
+}
+
+}  // namespace fvk

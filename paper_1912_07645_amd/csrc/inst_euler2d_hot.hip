@@ -1,0 +1,15 @@
+// 2D Euler WENO3 + HLLC (the Kelvin--Helmholtz configuration): tile shapes for the tuner.
+// Each shape's face list fills its wavefronts almost exactly (faces / lanes per pass):
+// 16x15: 511/512, 20x12: 512/512, 32x15 on 512 threads: 1007/1024, 32x7: 487/512.
+#include "fv_registry.h"
+#include "fv_stage.h"
+
+namespace fvk {
+static const RegEntry kTable[] = {
+    FV_ENTRY(2, EQ_EULER, REC_WENO3, FLUX_HLLC, 16, 15, 1, 256),
+    FV_ENTRY(2, EQ_EULER, REC_WENO3, FLUX_HLLC, 20, 12, 1, 256),
+    FV_ENTRY(2, EQ_EULER, REC_WENO3, FLUX_HLLC, 32, 15, 1, 512),
+    FV_ENTRY(2, EQ_EULER, REC_WENO3, FLUX_HLLC, 32, 7, 1, 256),
+};
+const RegEntry* unit_euler2d_hot(int* count) { *count = sizeof(kTable) / sizeof(kTable[0]); return kTable; }
+}  // namespace fvk

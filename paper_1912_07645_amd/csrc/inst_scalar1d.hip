@@ -1,0 +1,11 @@
+// 1D scalar equations (linear advection, Burgers): every reconstruction x (Rusanov, HLL).
+#include "fv_registry.h"
+#include "fv_stage.h"
+
+namespace fvk {
+static const RegEntry kTable[] = {
+    FV_ALL_RF(1, EQ_ADVECTION, 255, 1, 1, 256),
+    FV_ALL_RF(1, EQ_BURGERS, 255, 1, 1, 256),
+};
+const RegEntry* unit_scalar1d(int* count) { *count = sizeof(kTable) / sizeof(kTable[0]); return kTable; }
+}  // namespace fvk
