@@ -17,8 +17,11 @@ rate on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -57,6 +60,11 @@ WORKLOADS = {
 }
 
 
+# rocprofv3 summaries of the stage kernel (commands, counters, traffic) per workload
+PROFILE_SUMMARY = {"kh2d": "stage_kernel_kh2d_1024.md", "kh3d": "stage_kernel_kh3d_512.md",
+                   "mc": "stage_kernel_mc_256x1024.md"}
+
+
 def initial_state(w):
     import numpy as np
     import fv_inputs as fi
@@ -67,6 +75,29 @@ def initial_state(w):
         return fi.kh2d_state(w["n"], c, phi)
     cx, px, cz, pz = fi.kh3d_coefficients(w["seed"], np.arange(w["batch"]))
     return fi.kh3d_state(w["n"], cx, px, cz, pz)
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1912_07645_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per stage launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", PROFILE_SUMMARY.get(workload, "-"))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"sources_sha256:\s*([0-9a-f]+)", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.e+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_sources_hash():
+        return None
+    return float(m_val.group(1))
 
 
 def cpu_baseline(w, U0, steps):
@@ -108,6 +139,9 @@ def main():
     ap.add_argument("--workload", default="kh2d", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--variant", type=int, default=None, help="tile variant (default: tuned)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file remembering the tuned variant per workload")
     a = ap.parse_args()
 
     ws = int(os.environ.get("WORLD_SIZE", "1"))
@@ -137,7 +171,20 @@ def main():
     t = torch.zeros(B, dtype=torch.float64, device=dev)
     steps_t = torch.zeros(B, dtype=torch.int64, device=dev)
     err = torch.zeros(B, dtype=torch.int32, device=dev)
-    tuned = s.tune(U, reps=3) if s.num_variants() > 1 else 0
+    cache = {}
+    if a.tune_cache and os.path.exists(a.tune_cache):
+        cache = json.load(open(a.tune_cache))
+    if a.variant is not None:
+        s.set_variant(a.variant)
+        tuned = a.variant
+    elif w["name"] in cache:
+        tuned = int(cache[w["name"]])
+        s.set_variant(tuned)
+    else:
+        tuned = s.tune(U, reps=3) if s.num_variants() > 1 else 0
+        if a.tune_cache:
+            cache[w["name"]] = tuned
+            json.dump(cache, open(a.tune_cache, "w"))
     tile, _ = s.tile()
 
     t_end = 1e9
@@ -184,7 +231,8 @@ def main():
                    "cells_per_sample": cells, "cfl": w["cfl"], "seed": w["seed"],
                    "tile": list(tile), "tuned_variant": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(a.workload),
                      "kernel": "stage_kernel", "avg_launch_us": avg_launch_s * 1e6,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "hbm_frac_whole_step": bytes_step * K / el / 1e9 / HBM_PEAK_GBS,
