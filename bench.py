@@ -54,6 +54,10 @@ WORKLOADS = {
     "mc": dict(name="kh2d_256x256_x1024_samples_weno3_hllc_ssprk3", dim=2, n=256, flux="hllc",
                recon="weno3", integrator="ssprk3", cfl=0.4, batch=1024, seed=1912,
                steps=50, warmup=5, cpu_steps=2),
+    "mlmc": dict(name="mlmc_kh2d_64-512_4096-64_samples_muscl_hll_ssprk2", dim=2, n=512,
+                 flux="hll", recon="muscl_minmod", integrator="ssprk2", cfl=0.4, batch=64,
+                 seed=1913, steps=1, warmup=1, cpu_steps=2, t_end=1.0,
+                 ns=(64, 128, 256, 512), Ms=(4096, 1024, 256, 64)),
     "sod": dict(name="sod_1024_first_order_rusanov_forward_euler", dim=1, n=1024,
                 flux="rusanov", recon="first_order", integrator="forward_euler", cfl=0.45,
                 batch=1, seed=0, steps=1000, warmup=100, cpu_steps=1000),
@@ -131,6 +135,71 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 10}))
 
 
+def run_mlmc(a, w):
+    """The mixed multilevel batch: every level's groups evolved together to T = 1 in shared
+    launches, then level statistics and the estimate on the finest grid. One "step" here is one
+    whole multilevel run (the state is reloaded before each run, outside the timed region)."""
+    import numpy as np
+    import torch
+    import fv_inputs as fi
+    from paper_1912_07645_amd.mlmc import MultilevelRun
+
+    ns, Ms = w["ns"], w["Ms"]
+    groups = fi.mlmc_inputs(ns, Ms, seed=w["seed"])
+    run = MultilevelRun(ns, Ms, dim=2, eq="euler", flux=w["flux"], recon=w["recon"],
+                        integrator=w["integrator"], device="cuda:0")
+    K = a.steps if a.steps is not None else w["steps"]
+    W = a.warmup if a.warmup is not None else w["warmup"]
+    dev_groups = [torch.from_numpy(g).to("cuda:0") for g in groups]
+    times, cell_updates = [], 0
+    steps_per_grid = None
+    for r in range(W + K):
+        G = [g.clone() for g in dev_groups]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, ts, errs = run.evolve(G, w["t_end"], w["cfl"])
+        est, levels = run.statistics(G)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert st == 0
+        if r >= W:
+            times.append(el)
+        steps_per_grid = [int(k.sum()) for k in run.last_steps]
+    for l, n in enumerate(ns):
+        cell_updates += n * n * steps_per_grid[l]
+    el = sum(times) / len(times)
+    out = {
+        "metric": "FP64 cell-updates/s", "value": cell_updates / el, "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": el * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w["name"], "grids": list(ns), "samples_per_level": list(Ms),
+                   "samples_per_grid": [int(g.shape[0]) for g in groups],
+                   "sample_steps_per_grid": steps_per_grid, "t_end": w["t_end"],
+                   "cfl": w["cfl"], "seed": w["seed"],
+                   "step": "one whole multilevel run (all levels to T, statistics, estimate)"},
+        "mlmc_runs_per_s": 1.0 / el,
+        "roofline": None,
+    }
+    print(json.dumps(out))
+
+
+def per_sample_rate(s, U, cfl, K, B1):
+    """The same kernels with one sample per launch (the unbatched way), over B1 samples."""
+    import torch
+    t = torch.zeros(1, dtype=torch.float64, device=U.device)
+    k = torch.zeros(1, dtype=torch.int64, device=U.device)
+    Us = [U[b:b + 1].clone() for b in range(B1)]
+    s.advance(Us[0], t, 1e9, cfl, 2, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(B1):
+        t.zero_()
+        s.advance(Us[b], t, 1e9, cfl, K, k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return B1 * K / el, Us
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +221,9 @@ def main():
         sys.exit(2)
     if a.copy_calibration:
         copy_calibration()
+        return
+    if a.workload == "mlmc":
+        run_mlmc(a, WORKLOADS["mlmc"])
         return
 
     import numpy as np
@@ -238,7 +310,24 @@ def main():
         "hbm_frac_whole_step": bytes_step * K / el / 1e9 / HBM_PEAK_GBS,
     }
     if w["name"].startswith("kh2d_256x256_x1024"):
-        out["mc_samples_steps_per_s"] = B * K / el
+        from paper_1912_07645_amd import Stats
+        out["mc_sample_steps_per_s"] = B * K / el
+        # batched against per-sample launches of the same kernels, on the first 32 samples
+        U2 = torch.from_numpy(U0).to(dev)
+        t2 = torch.zeros(B, dtype=torch.float64, device=dev)
+        s.advance(U2[:32], t2[:32], 1e9, w["cfl"], 2)
+        single, Us = per_sample_rate(s, torch.from_numpy(U0[:32]).to(dev), w["cfl"], K, 32)
+        out["per_sample_launch_sample_steps_per_s"] = single
+        out["batched_speedup_over_per_sample_launches"] = (B * K / el) / single
+        # on-device statistics of the batch: Welford mean/variance of (rho, u, v, E) and S2(h),
+        # h = 1..32
+        st = Stats(s, max_h=32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.accumulate(U)
+        res = st.read()
+        torch.cuda.synchronize()
+        out["stats_ms_for_batch"] = (time.perf_counter() - t0) * 1e3
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, U0, w["cpu_steps"])
     print(json.dumps(out))

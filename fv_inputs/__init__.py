@@ -23,7 +23,8 @@ MASK64 = (1 << 64) - 1
 __all__ = [
     "mix64", "uniform_draws", "kh_coefficients", "kh3d_coefficients", "kh_delta",
     "sod_state", "riemann_state_1d", "kh2d_state", "kh3d_state", "constant_state",
-    "random_smooth_state", "sine_state_scalar", "cell_centres",
+    "random_smooth_state", "sine_state_scalar", "cell_centres", "mlmc_inputs",
+    "kh2d_state_and_jacobian",
 ]
 
 
@@ -222,3 +223,62 @@ def sine_state_scalar(n: int, k: int = 1, amp: float = 1.0, offset: float = 0.0,
     if dim == 2:
         return np.broadcast_to(u[None, None, None, None, :], (1, 1, 1, n, n)).copy()
     return np.broadcast_to(u[None, None, None, None, :], (1, 1, n, n, n)).copy()
+
+
+def mlmc_inputs(ns, Ms, seed: int = 1913, gamma: float = 1.4):
+    """Initial states of a multilevel Kelvin--Helmholtz run, one array per grid ("group").
+
+    Level l (grid ns[l], Ms[l] samples) draws the coefficients of samples
+    offset_l .. offset_l + Ms[l] - 1, offset_l = Ms[0] + ... + Ms[l-1]. Group l holds level l's
+    samples on grid ns[l], followed by level l+1's samples (the same coefficients) on grid ns[l]
+    as the coarse partners of the coupled pairs.
+    """
+    offs = np.concatenate([[0], np.cumsum(Ms)]).astype(np.int64)
+    groups = []
+    for l, n in enumerate(ns):
+        ids = list(range(offs[l], offs[l] + Ms[l]))
+        if l + 1 < len(ns):
+            ids += list(range(offs[l + 1], offs[l + 1] + Ms[l + 1]))
+        c, phi = kh_coefficients(seed, np.array(ids, dtype=np.int64))
+        groups.append(kh2d_state(n, c, phi, gamma))
+    return groups
+
+
+def kh2d_state_and_jacobian(n: int, c: np.ndarray, phi: np.ndarray, gamma: float = 1.4,
+                            a: float = 0.01):
+    """The 2D Kelvin--Helmholtz initial state together with its derivative tables.
+
+    The state depends on the coefficients theta = (c_1..c_K, phi_1..phi_K) only through the
+    interface displacement delta(x_i) of each column i. Returns (U0, D, E):
+      U0 [b][4][1][n][n]   the state (as kh2d_state);
+      D  [b][4][1][n][n]   dU0/d delta(x_i) for the cell's own column (nonzero only in the
+                           cells the two interfaces cross: df/d delta = +-1/dy there);
+      E  [b][n][2K]        d delta(x_i)/d theta_k: a sin(2 pi k x + phi_k) for c_k and
+                           a c_k cos(2 pi k x + phi_k) for phi_k.
+    """
+    c = np.atleast_2d(c)
+    phi = np.atleast_2d(phi)
+    U0 = kh2d_state(n, c, phi, gamma, a)
+    B, K = c.shape
+    xc = cell_centres(n)
+    dy = 1.0 / n
+    yj = np.arange(n, dtype=np.float64)
+    y_lo = (yj * dy)[None, :, None]
+    y_hi = ((yj + 1.0) * dy)[None, :, None]
+    delta = kh_delta(c, phi, xc, a)[:, None, :]
+    i1 = 0.25 + delta
+    i2 = 0.75 + delta
+    raw = (np.minimum(y_hi, i2) - np.maximum(y_lo, i1)) * float(n)
+    draw = (np.where(i2 < y_hi, 1.0, 0.0) - np.where(i1 > y_lo, 1.0, 0.0)) * float(n)
+    dfd = np.where((raw > 0.0) & (raw < 1.0), draw, 0.0)          # [b][ny][nx]
+    uin = _euler_conserved(2.0, 0.5, 0.0, 0.0, 2.5, gamma, 2)
+    uout = _euler_conserved(1.0, -0.5, 0.0, 0.0, 2.5, gamma, 2)
+    D = np.empty_like(U0)
+    for q in range(4):
+        D[:, q, 0] = dfd * (uin[q] - uout[q])
+    E = np.empty((B, n, 2 * K), dtype=np.float64)
+    for k in range(K):
+        arg = (2.0 * np.pi * (k + 1)) * xc[None, :] + phi[:, k:k + 1]
+        E[:, :, k] = a * np.sin(arg)
+        E[:, :, K + k] = a * c[:, k:k + 1] * np.cos(arg)
+    return U0, D, E

@@ -78,6 +78,7 @@ typedef struct {
 
 typedef struct fv_solver fv_solver;   /* opaque, library-owned */
 typedef struct fv_stats fv_stats;     /* opaque, library-owned */
+typedef struct fv_adjoint fv_adjoint; /* opaque, library-owned */
 
 /* ------------------------------------------------------------------ solver lifetime */
 
@@ -136,14 +137,16 @@ fv_status fv_evolve_fixed_dt(fv_solver* solver, double* state, int64_t batch, do
 
 /* Several solvers (grids of different resolution sharing one equation and scheme, e.g. the
  * levels of a multilevel Monte Carlo estimate, Section 2.2) evolved together: every
- * Runge--Kutta stage of all groups runs as one launch. Group g has solvers[g], its batch
- * states[g][batches[g]][fields][cells], times t[g] (device double[batches[g]]) and err[g]
- * (device int32[batches[g]], entries may be NULL). All solvers must share equation, flux,
- * reconstruction, integrator and dimension; their stream is that of solvers[0]. Semantics
- * per sample as in fv_evolve. */
+ * Runge--Kutta stage of all groups runs as one launch, each sample with its own time step.
+ * Group g (1 <= n_groups <= 8) has solvers[g] (distinct solvers), its batch
+ * states[g][batches[g]][fields][cells], times t[g] (device double[batches[g]]), step counts
+ * steps[g] (device int64[batches[g]]) and statuses err[g] (device int32[batches[g]]); steps
+ * and err, and their entries, may be NULL. All solvers must share dimension, boundary
+ * conditions, equation, flux, reconstruction, integrator and tile; the work runs on
+ * solvers[0]'s stream. Semantics per sample as in fv_evolve. */
 fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers, double* const* states,
                           const int64_t* batches, double* const* t, double t_end, double cfl,
-                          int64_t max_steps, int32_t* const* err);
+                          int64_t max_steps, int64_t* const* steps, int32_t* const* err);
 
 /* ------------------------------------------------------------------ tile tuning */
 
@@ -194,10 +197,71 @@ fv_status fv_stats_accumulate(fv_stats* stats, const double* state, int64_t batc
 fv_status fv_stats_read(const fv_stats* stats, double* mean, double* var, double* s2_mean,
                         double* s2_var, int64_t* count);
 
+/* Multilevel Monte Carlo (Section 2.2): sum_l (1/M_l) sum_k (G(u^l_k) - G(u^{l-1}_k)).
+ * fv_stats_accumulate_diff adds coupled samples (the same random input evolved on the
+ * stats' fine grid and on a coarser grid) in index order: per fine cell, Welford updates of
+ * x = q(u_fine) - P q(u_coarse), where P copies each coarse cell onto the fine cells it
+ * contains (piecewise-constant prolongation). fine: device double[batch][fields][fine
+ * cells]; coarse_state: device double[batch][fields][coarse cells] on coarse's grid, which
+ * must divide the fine grid on every axis (FV_EINVAL otherwise); the stats must have max_h
+ * = 0 (FV_ENOTSUP otherwise). The first level (u^0 = 0) uses fv_stats_accumulate. */
+fv_status fv_stats_accumulate_diff(fv_stats* stats, const double* fine, const fv_solver* coarse,
+                                   const double* coarse_state, int64_t batch);
+
+/* The multilevel estimate on the finest grid: out[q][cell] = sum_{l = 1..L} P_{l -> L}
+ * mean_l, with levels[0..L-1] ordered coarse to fine (levels[L-1] on the finest grid) and
+ * added in that order. out: device double[quantities][finest cells]. Synchronises. */
+fv_status fv_mlmc_combine(int32_t nlevels, const fv_stats* const* levels, double* out);
+
 /* Reset to zero samples. */
 fv_status fv_stats_reset(fv_stats* stats);
 
 fv_status fv_stats_destroy(fv_stats* stats);
+
+/* ------------------------------------------------------------------ discrete adjoint */
+
+/* Discrete adjoint of a fixed-step run (not in the paper; it differentiates the scheme of
+ * Section 2.1). The forward map is nsteps SSP Runge--Kutta steps of size dt; the adjoint is
+ * the exact transpose of its linearisation, with the forward pass's branch choices (the
+ * larger Rusanov wave speed, ties to the right state; the minmod argument selected; the
+ * derivative of |u| at 0 taken as 0). Supported: the Euler equations in 1D and 2D with the
+ * Rusanov flux and first-order or MUSCL-minmod reconstruction (FV_ENOTSUP otherwise).
+ *
+ * fv_adjoint_create allocates, for `batch` samples of the solver's grid, ceil(nsteps/every)
+ * checkpoint states, every * stages + 1 segment states and three adjoint states (device
+ * memory owned by the handle). every <= 0 selects ceil(sqrt(nsteps)). cfl_bound is checked
+ * over the whole forward trajectory (dt * max wave speed). */
+fv_status fv_adjoint_create(fv_solver* solver, int64_t batch, int64_t nsteps, double dt,
+                            int64_t every, double cfl_bound, fv_adjoint** out);
+
+/* Forward run from state0 (device, [batch][fields][cells], not modified) to stateT (device,
+ * same shape), storing checkpoints. FV_ENONPHYS / FV_ECFL if a sample's trajectory left the
+ * physical states or the CFL bound. */
+fv_status fv_adjoint_forward(fv_adjoint* adj, const double* state0, double* stateT);
+
+/* Reverse sweep: dQ/dU0 (device, [batch][fields][cells], written) from dQ/dUT (device, same
+ * shape, not modified), recomputing each checkpoint segment. Needs a completed
+ * fv_adjoint_forward. */
+fv_status fv_adjoint_backward(fv_adjoint* adj, const double* dQ_dUT, double* dQ_dU0);
+
+fv_status fv_adjoint_destroy(fv_adjoint* adj);
+
+/* Quantity of interest: the kinetic energy sum 0.5 |m|^2 / rho times the cell volume, over the
+ * cells whose index along axis 1 lies in [j0, j1) (all cells of those rows), per sample:
+ * Q[b] (device double[batch], may be NULL). If dQ_dU (device, state-shaped) is given, it
+ * receives seed[b] * dQ[b]/dU (seed: device double[batch], required then), zero outside the
+ * band. Euler equations only. Sums use a fixed order (reproducible). */
+fv_status fv_qoi_kinetic_energy(fv_solver* solver, const double* state, int64_t batch, int64_t j0,
+                                int64_t j1, const double* seed, double* Q, double* dQ_dU);
+
+/* Chain rule through initial data that depends on parameters theta through one scalar per
+ * line along axis 1 (a line: fixed x and z indices, e.g. the displaced interface of a shear
+ * layer): out[b][k] = sum_lines (sum_{cells of the line} sum_fields lambda0 * dU_dline)
+ * * dline_dtheta[b][line][k]. lambda0, dU_dline: device [batch][fields][cells];
+ * dline_dtheta: device [batch][lines = n[2] * n[0], z slowest][ntheta]; out: device
+ * [batch][ntheta]. Fixed summation order. */
+fv_status fv_line_vjp(fv_solver* solver, const double* lambda0, const double* dU_dline,
+                      const double* dline_dtheta, int32_t ntheta, int64_t batch, double* out);
 
 /* ------------------------------------------------------------------ misc */
 

@@ -79,6 +79,9 @@ def lib():
         L.oc_stats_accumulate.argtypes = [P, dp, C.c_int64, C.c_int32, dp, dp, dp, dp,
                                           C.POINTER(C.c_int64)]
         L.oc_set_threads.argtypes = [C.c_int]
+        L.oc_stats_accumulate_diff.argtypes = [P, P, dp, dp, C.c_int64, dp, dp,
+                                               C.POINTER(C.c_int64)]
+        L.oc_mlmc_combine.argtypes = [C.c_int32, P, C.POINTER(dp), dp]
         _lib = L
     return _lib
 
@@ -230,6 +233,49 @@ def structure_function(p: Problem, q: np.ndarray, h: int) -> float:
     q = np.ascontiguousarray(q, dtype=np.float64)
     assert q.size == p.cells
     return lib().oc_structure_function(p.c, _dp(q), int(h))
+
+
+class LevelStats:
+    """Per-cell moments over coupled samples of q(u_fine) - P q(u_coarse) (one MLMC level);
+    with coarse=None, plain moments of q(u_fine) (the first level, u^0 = 0)."""
+
+    def __init__(self, fine: Problem, coarse: "Problem | None" = None):
+        self.fine, self.coarse = fine, coarse
+        self.mean = np.zeros((fine.nfields,) + fine.state_shape[1:], dtype=np.float64)
+        self.m2 = np.zeros_like(self.mean)
+        self.count = C.c_int64(0)
+        self._plain = Stats(fine, 0) if coarse is None else None
+
+    def accumulate(self, Uf: np.ndarray, Uc: np.ndarray | None = None):
+        if self._plain is not None:
+            self._plain.accumulate(Uf)
+            self.mean, self.m2, self.count = self._plain.mean, self._plain.m2, self._plain.count
+            return
+        Uf = np.ascontiguousarray(Uf, dtype=np.float64)
+        Uc = np.ascontiguousarray(Uc, dtype=np.float64)
+        assert Uf.shape[0] == Uc.shape[0]
+        rc = lib().oc_stats_accumulate_diff(self.fine.c, self.coarse.c, _dp(Uf), _dp(Uc),
+                                            Uf.shape[0], _dp(self.mean), _dp(self.m2),
+                                            C.byref(self.count))
+        _check(rc, "oc_stats_accumulate_diff")
+
+    @property
+    def n(self) -> int:
+        return self.count.value
+
+    def variance(self, ddof: int = 0):
+        return self.m2 / (self.n - ddof)
+
+
+def mlmc_combine(levels) -> np.ndarray:
+    """sum_l P_{l -> L} mean_l on the finest (last) level's grid."""
+    L = len(levels)
+    arr = (OcProblem * L)(*[lv.fine._c for lv in levels])
+    means = [np.ascontiguousarray(lv.mean) for lv in levels]
+    ptrs = (C.POINTER(C.c_double) * L)(*[_dp(m) for m in means])
+    out = np.empty_like(means[-1])
+    _check(lib().oc_mlmc_combine(L, arr, ptrs, _dp(out)), "oc_mlmc_combine")
+    return out
 
 
 class Stats:

@@ -657,6 +657,92 @@ int oc_stats_accumulate(const oc_problem* P, const double* U, int64_t batch, int
     return OC_OK;
 }
 
+/* ---------------------------------------------------------------- multilevel Monte Carlo */
+
+/* Integer refinement ratio of a fine grid over a coarse grid on every axis (0 if not an
+ * integer ratio >= 1 on every active axis). */
+static int refinement(const oc_problem* F, const oc_problem* Cp, int64_t r[3])
+{
+    if (F->dim != Cp->dim || oc_num_fields(F) != oc_num_fields(Cp)) return 0;
+    for (int k = 0; k < 3; ++k) {
+        if (Cp->n[k] < 1 || F->n[k] % Cp->n[k] != 0) return 0;
+        r[k] = F->n[k] / Cp->n[k];
+    }
+    return 1;
+}
+
+/* Index of the coarse cell that contains fine cell (i, j, k) (piecewise-constant
+ * prolongation P: every fine cell takes the value of its parent). */
+static int64_t parent_cell(const oc_problem* Cp, const int64_t r[3], int64_t i, int64_t j,
+                           int64_t k)
+{
+    return ((k / r[2]) * Cp->n[1] + (j / r[1])) * Cp->n[0] + (i / r[0]);
+}
+
+/* Level-difference statistics of the multilevel estimator (Section 2.2): for coupled
+ * samples b (the same random input on the fine and the coarse grid), the per-cell running
+ * moments of x = q(u_fine) - P q(u_coarse), samples added in index order. mean and m2 live on
+ * the fine grid: [quantity][fine cells]. */
+int oc_stats_accumulate_diff(const oc_problem* F, const oc_problem* Cp, const double* Uf,
+                             const double* Uc, int64_t batch, double* mean, double* m2,
+                             int64_t* count)
+{
+    int st = oc_validate(F);
+    if (st) return st;
+    st = oc_validate(Cp);
+    if (st) return st;
+    int64_t r[3];
+    if (!refinement(F, Cp, r)) return OC_EINVAL;
+    const int nf = oc_num_fields(F);
+    const int64_t Nf = cells_of(F), Nc = cells_of(Cp);
+    double* qf = (double*)malloc(sizeof(double) * (size_t)(Nf * nf));
+    double* qc = (double*)malloc(sizeof(double) * (size_t)(Nc * nf));
+    if (!qf || !qc) { free(qf); free(qc); return OC_ENOMEM; }
+    for (int64_t b = 0; b < batch; ++b) {
+        oc_quantities(F, Uf + b * Nf * nf, qf);
+        oc_quantities(Cp, Uc + b * Nc * nf, qc);
+        const int64_t n = *count + 1;
+        for (int q = 0; q < nf; ++q)
+            for (int64_t k = 0; k < F->n[2]; ++k)
+                for (int64_t j = 0; j < F->n[1]; ++j)
+                    for (int64_t i = 0; i < F->n[0]; ++i) {
+                        const int64_t c = (k * F->n[1] + j) * F->n[0] + i;
+                        const double x = qf[q * Nf + c] - qc[q * Nc + parent_cell(Cp, r, i, j, k)];
+                        welford(x, n, &mean[q * Nf + c], &m2[q * Nf + c]);
+                    }
+        *count = n;
+    }
+    free(qf);
+    free(qc);
+    return OC_OK;
+}
+
+/* Multilevel estimate on the finest grid: out = sum_{l = 1..L} P_{l -> L} mean_l, levels added
+ * in order (level 1 holds the plain mean, since u^0 = 0). probs[l], means[l] = [quantity][cells
+ * of level l]; the last level is the finest. */
+int oc_mlmc_combine(int32_t nlevels, const oc_problem* probs, const double* const* means,
+                    double* out)
+{
+    if (nlevels < 1) return OC_EINVAL;
+    const oc_problem* Fp = &probs[nlevels - 1];
+    const int nf = oc_num_fields(Fp);
+    const int64_t Nf = cells_of(Fp);
+    for (int l = 0; l < nlevels; ++l) {
+        int64_t r[3];
+        if (!refinement(Fp, &probs[l], r)) return OC_EINVAL;
+        const int64_t Nl = cells_of(&probs[l]);
+        for (int q = 0; q < nf; ++q)
+            for (int64_t k = 0; k < Fp->n[2]; ++k)
+                for (int64_t j = 0; j < Fp->n[1]; ++j)
+                    for (int64_t i = 0; i < Fp->n[0]; ++i) {
+                        const int64_t c = (k * Fp->n[1] + j) * Fp->n[0] + i;
+                        const double v = means[l][q * Nl + parent_cell(&probs[l], r, i, j, k)];
+                        out[q * Nf + c] = (l == 0) ? v : (out[q * Nf + c] + v);
+                    }
+    }
+    return OC_OK;
+}
+
 /* ---------------------------------------------------------------- misc */
 
 int oc_set_threads(int n)

@@ -8,12 +8,12 @@ loaded on first use of any of these names and raises ImportError if libfv.so is 
 """
 import importlib
 
-__all__ = ["fv", "Solver", "Stats", "evolve_multi"]
+__all__ = ["fv", "Solver", "Stats", "evolve_multi", "mlmc_combine"]
 
 
 def __getattr__(name):
     if name == "fv":
         return importlib.import_module(".fv", __name__)
-    if name in ("Solver", "Stats", "evolve_multi"):
+    if name in ("Solver", "Stats", "evolve_multi", "mlmc_combine"):
         return getattr(importlib.import_module(".solver", __name__), name)
     raise AttributeError(name)

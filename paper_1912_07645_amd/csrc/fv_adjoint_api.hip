@@ -1,0 +1,340 @@
+// fv_adjoint_api.hip -- host side of the discrete adjoint: fixed-dt forward run with
+// checkpoints, reverse sweep with per-segment recomputation, the kinetic-energy quantity of
+// interest and the line-wise contraction with the initial-data derivative.
+//
+// Checkpointing: the state is stored every `every` steps (every = ceil(sqrt(nsteps)) gives
+// the classical sqrt(N) scheme). The reverse sweep takes the segments last to first; each
+// is recomputed forward from its checkpoint with all Runge--Kutta stage states stored, then
+// reversed stage by stage. Memory: ceil(N / every) + every * stages + 4 states per batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <new>
+#include <vector>
+
+#include "fv_adjoint.h"
+#include "fv_host.h"
+
+using namespace fvk;
+
+struct fv_adjoint {
+    fv_solver* s = nullptr;
+    const AdjKernel* ak = nullptr;
+    int64_t batch = 0, nsteps = 0, every = 0, nseg = 0;
+    double dt = 0.0, cfl_bound = 0.0;
+    int nst = 0;
+    size_t state_doubles = 0;      // doubles per batch state
+    double* ckpt = nullptr;        // nseg states
+    double* seg = nullptr;         // every * nst + 1 states
+    double* lam[3] = {nullptr, nullptr, nullptr};
+    double* dt_arr = nullptr;      // [batch]
+    int32_t* active = nullptr;     // [batch], all 1
+    unsigned long long* mbits = nullptr;
+    int32_t* bad = nullptr;
+    bool forward_done = false;
+};
+
+static __global__ void adj_init_kernel(double* dt_arr, int32_t* active, unsigned long long* mbits,
+                                       int32_t* bad, int64_t batch, double dt)
+{
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < batch;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        dt_arr[b] = dt;
+        active[b] = 1;
+        mbits[b] = 0ull;
+        bad[b] = 0;
+    }
+}
+
+static Group stage_group(const fv_adjoint* a, const double* src, const double* un, double* dst)
+{
+    const fv_solver* s = a->s;
+    Group g{};
+    g.src = src;
+    g.un = un;
+    g.dst = dst;
+    g.dt = a->dt_arr;
+    g.active = a->active;
+    g.mbits = a->mbits;
+    g.bad = a->bad;
+    g.cells = s->cells;
+    const int32_t tb[3] = {s->kern->bx, s->kern->by, s->kern->bz};
+    g.ntiles = 1;
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = (int32_t)s->grid.n[k];
+        g.tiles[k] = (int32_t)((s->grid.n[k] + tb[k] - 1) / tb[k]);
+        g.ntiles *= g.tiles[k];
+    }
+    g.batch = (int32_t)a->batch;
+    g.block0 = 0;
+    g.ph = s->ph;
+    return g;
+}
+
+// One forward step from `un` with stage outputs to dst[0..nst-1] (dst[nst-1] = next state).
+static void forward_step(const fv_adjoint* a, const double* un, double* const* dst)
+{
+    const fv_solver* s = a->s;
+    const double* src = un;
+    for (int st = 0; st < a->nst; ++st) {
+        StageArgs sa{};
+        sa.ngroups = 1;
+        sa.g[0] = stage_group(a, src, un, dst[st]);
+        for (int k = 0; k < 3; ++k) sa.bc[k] = s->grid.bc[k];
+        sa.beta = stage_beta(s->integ, st);
+        sa.use_un = st > 0;
+        sa.last = (st == a->nst - 1);
+        sa.nblocks = (int64_t)sa.g[0].ntiles * a->batch;
+        s->kern->stage(sa, s->stream);
+        src = dst[st];
+    }
+}
+
+extern "C" fv_status fv_adjoint_create(fv_solver* s, int64_t batch, int64_t nsteps, double dt,
+                                       int64_t every, double cfl_bound, fv_adjoint** out)
+{
+    if (!s || !out) return fail(FV_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (batch < 1 || nsteps < 1) return fail(FV_EINVAL, "batch and nsteps must be >= 1");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FV_EINVAL, "dt must be > 0");
+    if (!(cfl_bound > 0.0)) return fail(FV_EINVAL, "cfl_bound must be > 0");
+    const AdjKernel* ak = find_adjoint_kernel(s->grid.dim, s->eq.kind, s->recon, s->flux);
+    if (!ak)
+        return fail(FV_ENOTSUP, "the adjoint covers the Euler equations in 1D/2D with the Rusanov "
+                                "flux and first-order or MUSCL-minmod reconstruction");
+    if (every <= 0) every = (int64_t)std::ceil(std::sqrt((double)nsteps));
+    every = std::min(every, nsteps);
+    const int64_t tiles = [&] {
+        int64_t n = 1;
+        const int32_t tb[3] = {ak->bx, ak->by, ak->bz};
+        for (int k = 0; k < 3; ++k) n *= (s->grid.n[k] + tb[k] - 1) / tb[k];
+        return n;
+    }();
+    if (tiles * batch > 0x7fffffffLL) return fail(FV_EINVAL, "launch too large");
+    fv_adjoint* a = new (std::nothrow) fv_adjoint();
+    if (!a) return fail(FV_ENOMEM, "host allocation failed");
+    a->s = s;
+    a->ak = ak;
+    a->batch = batch;
+    a->nsteps = nsteps;
+    a->every = every;
+    a->nseg = (nsteps + every - 1) / every;
+    a->dt = dt;
+    a->cfl_bound = cfl_bound;
+    a->nst = n_stages(s->integ);
+    a->state_doubles = (size_t)batch * s->nf * s->cells;
+    const size_t sb = sizeof(double) * a->state_doubles;
+    bool ok = hipSetDevice(s->device) == hipSuccess &&
+              hipMalloc((void**)&a->ckpt, sb * a->nseg) == hipSuccess &&
+              hipMalloc((void**)&a->seg, sb * (every * a->nst + 1)) == hipSuccess &&
+              hipMalloc((void**)&a->lam[0], sb) == hipSuccess &&
+              hipMalloc((void**)&a->lam[1], sb) == hipSuccess &&
+              hipMalloc((void**)&a->lam[2], sb) == hipSuccess &&
+              hipMalloc((void**)&a->dt_arr, sizeof(double) * batch) == hipSuccess &&
+              hipMalloc((void**)&a->active, sizeof(int32_t) * batch) == hipSuccess &&
+              hipMalloc((void**)&a->mbits, sizeof(unsigned long long) * batch) == hipSuccess &&
+              hipMalloc((void**)&a->bad, sizeof(int32_t) * batch) == hipSuccess;
+    if (!ok) {
+        fv_adjoint_destroy(a);
+        return fail(FV_ENOMEM, "adjoint allocation failed");
+    }
+    *out = a;
+    return FV_OK;
+}
+
+extern "C" fv_status fv_adjoint_destroy(fv_adjoint* a)
+{
+    if (!a) return FV_OK;
+    if (a->s && a->s->stream) hipStreamSynchronize(a->s->stream);
+    hipFree(a->ckpt);
+    hipFree(a->seg);
+    for (double* l : a->lam) hipFree(l);
+    hipFree(a->dt_arr);
+    hipFree(a->active);
+    hipFree(a->mbits);
+    hipFree(a->bad);
+    delete a;
+    return FV_OK;
+}
+
+extern "C" fv_status fv_adjoint_forward(fv_adjoint* a, const double* state0, double* stateT)
+{
+    if (!a || !state0 || !stateT) return fail(FV_EINVAL, "NULL argument");
+    fv_solver* s = a->s;
+    HIP_TRY(hipSetDevice(s->device));
+    fv_status e = stream_enter(s);
+    if (e) return e;
+    hipStream_t st = s->stream;
+    const size_t sb = sizeof(double) * a->state_doubles;
+    hipLaunchKernelGGL(adj_init_kernel, dim3(64), dim3(256), 0, st, a->dt_arr, a->active, a->mbits,
+                       a->bad, a->batch, a->dt);
+    {   // wave speed and physicality of the initial state
+        SpeedArgs sp{};
+        sp.ngroups = 1;
+        sp.g[0] = stage_group(a, state0, state0, nullptr);
+        sp.nblocks = ((s->cells + s->kern->cells_per_block - 1) / s->kern->cells_per_block) * a->batch;
+        s->kern->speed(sp, st);
+    }
+    // rolling buffers: seg[0] holds the current state, seg[1..] the stage states
+    double* cur = a->seg;
+    HIP_TRY(hipMemcpyAsync(cur, state0, sb, hipMemcpyDeviceToDevice, st));
+    std::vector<double*> dst(a->nst);
+    for (int k = 0; k < a->nst - 1; ++k) dst[k] = a->seg + (size_t)(k + 1) * a->state_doubles;
+    double* other = a->seg + (size_t)a->nst * a->state_doubles;  // forward Euler needs a second buffer
+    for (int64_t n = 0; n < a->nsteps; ++n) {
+        if (n % a->every == 0)
+            HIP_TRY(hipMemcpyAsync(a->ckpt + (size_t)(n / a->every) * a->state_doubles, cur, sb,
+                                   hipMemcpyDeviceToDevice, st));
+        if (a->nst == 1) {
+            dst[0] = other;
+            forward_step(a, cur, dst.data());
+            std::swap(cur, other);
+        } else {
+            dst[a->nst - 1] = cur;   // last stage writes U^{n+1} in place over U^n
+            forward_step(a, cur, dst.data());
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(stateT, cur, sb, hipMemcpyDeviceToDevice, st));
+    // trajectory checks: max wave speed over all states, non-physical values
+    std::vector<unsigned long long> mb((size_t)a->batch);
+    std::vector<int32_t> bd((size_t)a->batch);
+    HIP_TRY(hipMemcpyAsync(mb.data(), a->mbits, sizeof(unsigned long long) * a->batch, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(bd.data(), a->bad, sizeof(int32_t) * a->batch, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    a->forward_done = true;
+    e = stream_leave(s);
+    if (e) return e;
+    for (int64_t b = 0; b < a->batch; ++b) {
+        double M;
+        std::memcpy(&M, &mb[(size_t)b], sizeof(double));
+        if (bd[(size_t)b]) return fail(FV_ENONPHYS, "sample " + std::to_string(b) + " became non-physical");
+        if (a->dt * M > a->cfl_bound)
+            return fail(FV_ECFL, "sample " + std::to_string(b) + ": dt * max speed exceeded the bound");
+    }
+    return FV_OK;
+}
+
+static fv_status reverse_stage(fv_adjoint* a, const double* U, const double* lam, double* prev,
+                               double* acc, int mode, double beta)
+{
+    const fv_solver* s = a->s;
+    AdjArgs g{};
+    g.U = U;
+    g.lam = lam;
+    g.prev = prev;
+    g.acc = acc;
+    g.cells = s->cells;
+    g.ntiles = 1;
+    const int32_t tb[3] = {a->ak->bx, a->ak->by, a->ak->bz};
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = (int32_t)s->grid.n[k];
+        g.tiles[k] = (int32_t)((s->grid.n[k] + tb[k] - 1) / tb[k]);
+        g.ntiles *= g.tiles[k];
+        g.bc[k] = s->grid.bc[k];
+    }
+    g.batch = (int32_t)a->batch;
+    g.mode = mode;
+    g.beta = beta;
+    g.dt = a->dt;
+    g.nblocks = (int64_t)g.ntiles * a->batch;
+    g.ph = s->ph;
+    a->ak->launch(g, s->stream);
+    return FV_OK;
+}
+
+extern "C" fv_status fv_adjoint_backward(fv_adjoint* a, const double* dQ_dUT, double* dQ_dU0)
+{
+    if (!a || !dQ_dUT || !dQ_dU0) return fail(FV_EINVAL, "NULL argument");
+    if (!a->forward_done) return fail(FV_EINVAL, "fv_adjoint_forward must run first");
+    fv_solver* s = a->s;
+    HIP_TRY(hipSetDevice(s->device));
+    fv_status e = stream_enter(s);
+    if (e) return e;
+    hipStream_t st = s->stream;
+    const size_t sb = sizeof(double) * a->state_doubles;
+    const size_t sd = a->state_doubles;
+    const int S = a->nst;
+    int cur = 0;   // lam[cur] holds dQ/dU^{n+1}
+    HIP_TRY(hipMemcpyAsync(a->lam[cur], dQ_dUT, sb, hipMemcpyDeviceToDevice, st));
+    auto slot = [&](int64_t t, int k) { return a->seg + ((size_t)t * S + k) * sd; };
+    for (int64_t sg = a->nseg - 1; sg >= 0; --sg) {
+        const int64_t k0 = sg * a->every;
+        const int64_t K = std::min(a->every, a->nsteps - k0);
+        // recompute the segment, keeping every stage state
+        HIP_TRY(hipMemcpyAsync(slot(0, 0), a->ckpt + (size_t)sg * sd, sb, hipMemcpyDeviceToDevice, st));
+        std::vector<double*> dst(S);
+        for (int64_t t = 0; t < K; ++t) {
+            for (int k = 0; k < S - 1; ++k) dst[k] = slot(t, k + 1);
+            dst[S - 1] = slot(t + 1, 0);
+            forward_step(a, slot(t, 0), dst.data());
+        }
+        // reverse the segment's steps
+        for (int64_t t = K - 1; t >= 0; --t) {
+            int in = cur, p = (cur + 1) % 3, acc = (cur + 2) % 3;
+            if (S == 1) {
+                reverse_stage(a, slot(t, 0), a->lam[in], a->lam[p], a->lam[acc], 0, 1.0);
+                cur = p;
+                continue;
+            }
+            for (int stg = S - 1; stg >= 0; --stg) {
+                const double beta = stage_beta(s->integ, stg);
+                const int mode = (stg == S - 1) ? 0 : (stg == 0 ? 2 : 1);
+                reverse_stage(a, slot(t, stg), a->lam[in], a->lam[p], a->lam[acc], mode, beta);
+                std::swap(in, p);   // this stage's output is the next stage's input
+            }
+            cur = in;
+        }
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipMemcpyAsync(dQ_dU0, a->lam[cur], sb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return stream_leave(s);
+}
+
+extern "C" fv_status fv_qoi_kinetic_energy(fv_solver* s, const double* state, int64_t batch,
+                                           int64_t j0, int64_t j1, const double* seed, double* Q,
+                                           double* dQ_dU)
+{
+    if (!s || !state) return fail(FV_EINVAL, "NULL argument");
+    if (s->eq.kind != FV_EQ_EULER) return fail(FV_ENOTSUP, "kinetic energy needs the Euler equations");
+    if (batch < 1 || batch > 65535) return fail(FV_EINVAL, "batch must be in [1, 65535]");
+    if (j0 < 0 || j1 < j0 || j1 > s->grid.n[1]) return fail(FV_EINVAL, "band outside the grid");
+    if (dQ_dU && !seed) return fail(FV_EINVAL, "the gradient needs a seed");
+    HIP_TRY(hipSetDevice(s->device));
+    const int nblk = qoi_blocks(s->cells);
+    fv_status e = ensure_scratch(s, sizeof(double) * (size_t)nblk * batch);
+    if (e) return e;
+    e = stream_enter(s);
+    if (e) return e;
+    double volume = 1.0;
+    for (int k = 0; k < s->grid.dim; ++k) volume = volume * ((s->grid.hi[k] - s->grid.lo[k]) / (double)s->grid.n[k]);
+    const int32_t n32[3] = {(int32_t)s->grid.n[0], (int32_t)s->grid.n[1], (int32_t)s->grid.n[2]};
+    launch_qoi_ke(state, s->grid.dim, n32, (int32_t)batch, (int32_t)j0, (int32_t)j1, volume, seed, Q,
+                  dQ_dU, (double*)s->scratch, nblk, s->stream);
+    HIP_TRY(hipGetLastError());
+    return stream_leave(s);
+}
+
+extern "C" fv_status fv_line_vjp(fv_solver* s, const double* lambda0, const double* dU_dline,
+                                 const double* dline_dtheta, int32_t ntheta, int64_t batch,
+                                 double* out)
+{
+    if (!s || !lambda0 || !dU_dline || !dline_dtheta || !out) return fail(FV_EINVAL, "NULL argument");
+    if (ntheta < 1 || batch < 1) return fail(FV_EINVAL, "ntheta and batch must be >= 1");
+    if (s->grid.dim < 2) return fail(FV_EINVAL, "lines run along axis 1: dim must be >= 2");
+    HIP_TRY(hipSetDevice(s->device));
+    const int64_t lines = s->grid.n[0] * s->grid.n[2];
+    fv_status e = ensure_scratch(s, sizeof(double) * (size_t)(lines * batch));
+    if (e) return e;
+    e = stream_enter(s);
+    if (e) return e;
+    const int32_t n32[3] = {(int32_t)s->grid.n[0], (int32_t)s->grid.n[1], (int32_t)s->grid.n[2]};
+    launch_line_vjp(lambda0, dU_dline, dline_dtheta, s->nf, n32, (int32_t)batch, ntheta,
+                    (double*)s->scratch, out, s->stream);
+    HIP_TRY(hipGetLastError());
+    return stream_leave(s);
+}

@@ -20,27 +20,15 @@
 #include "../../include/fv.h"
 #include "fv_common.h"
 #include "fv_control.h"
+#include "fv_host.h"
 #include "fv_registry.h"
 #include "fv_stats.h"
 
 using namespace fvk;
 
+thread_local std::string g_last_error;
+
 // ------------------------------------------------------------------ errors
-
-static thread_local std::string g_last_error;
-
-static fv_status fail(fv_status st, const std::string& msg)
-{
-    g_last_error = msg;
-    return st;
-}
-
-#define HIP_TRY(expr)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(FV_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
-    } while (0)
 
 extern "C" const char* fv_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char* fv_version(void) { return "libfv 0.1 (gfx950)"; }
@@ -89,36 +77,6 @@ const StageKernel* find_stage_kernel(int dim, int eq, int recon, int flux, int v
 
 // ------------------------------------------------------------------ solver
 
-struct GraphCache {
-    hipGraphExec_t exec = nullptr;
-    std::vector<char> key;
-};
-
-struct fv_solver {
-    fv_grid grid;
-    fv_equation eq;
-    int32_t flux, recon, integ;
-    int32_t nf;
-    int64_t cells;
-    int32_t variant;
-    const StageKernel* kern;
-    Phys ph;
-    int device;
-    hipStream_t user_stream = nullptr;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
-    bool ws_owned = true;
-    int32_t* host_count = nullptr;  // pinned
-    GraphCache graph;
-    // kernel timing (fv_profile_enable)
-    bool profile = false;
-    std::vector<hipEvent_t> prof_ev;
-    double prof_stage_ms = 0.0;
-    int64_t prof_stage_launches = 0;
-};
-
 struct fv_stats {
     const fv_solver* s;
     int32_t max_h;
@@ -132,20 +90,6 @@ struct fv_stats {
     double* partial = nullptr;  // structure-function partial sums of a chunk
     int32_t chunk;
 };
-
-static int n_stages(int integ) { return integ == FV_INT_FORWARD_EULER ? 1 : (integ == FV_INT_SSPRK2 ? 2 : 3); }
-
-static double stage_beta(int integ, int s)
-{
-    if (s == 0) return 1.0;
-    if (integ == FV_INT_SSPRK2) return 0.5;
-    return (s == 1) ? 0.25 : (2.0 / 3.0);
-}
-
-// Stage buffers: RK3 needs U^(1) and U^(2); RK2 and forward Euler need one.
-static int n_stage_buffers(int integ) { return integ == FV_INT_SSPRK3 ? 2 : 1; }
-
-static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct WsLayout {
     size_t stage[2];
@@ -263,19 +207,13 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     return FV_OK;
 }
 
-static void drop_graph(fv_solver* s)
-{
-    if (s->graph.exec) hipGraphExecDestroy(s->graph.exec);
-    s->graph.exec = nullptr;
-    s->graph.key.clear();
-}
-
 extern "C" fv_status fv_destroy(fv_solver* s)
 {
     if (!s) return FV_OK;
     if (s->stream) hipStreamSynchronize(s->stream);
     drop_graph(s);
     for (hipEvent_t e : s->prof_ev) hipEventDestroy(e);
+    if (s->scratch) hipFree(s->scratch);
     if (s->ws && s->ws_owned) hipFree(s->ws);
     if (s->host_count) hipHostFree(s->host_count);
     if (s->ev) hipEventDestroy(s->ev);
@@ -327,21 +265,6 @@ static fv_status ensure_workspace(fv_solver* s, size_t need)
     if (hipMalloc(&p, need) != hipSuccess) return fail(FV_ENOMEM, "workspace allocation failed");
     s->ws = p;
     s->ws_bytes = need;
-    return FV_OK;
-}
-
-// Order the private stream after the caller's stream, and the caller's after ours.
-static fv_status stream_enter(fv_solver* s)
-{
-    HIP_TRY(hipEventRecord(s->ev, s->user_stream));
-    HIP_TRY(hipStreamWaitEvent(s->stream, s->ev, 0));
-    return FV_OK;
-}
-
-static fv_status stream_leave(fv_solver* s)
-{
-    HIP_TRY(hipEventRecord(s->ev, s->stream));
-    HIP_TRY(hipStreamWaitEvent(s->user_stream, s->ev, 0));
     return FV_OK;
 }
 
@@ -662,7 +585,8 @@ extern "C" fv_status fv_evolve_fixed_dt(fv_solver* s, double* state, int64_t bat
 extern "C" fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers,
                                      double* const* states, const int64_t* batches,
                                      double* const* t, double t_end, double cfl,
-                                     int64_t max_steps, int32_t* const* err)
+                                     int64_t max_steps, int64_t* const* steps,
+                                     int32_t* const* err)
 {
     if (n_groups < 1 || n_groups > kMaxGroups) return fail(FV_EINVAL, "n_groups must be in [1, 8]");
     if (!solvers || !states || !batches || !t) return fail(FV_EINVAL, "NULL argument");
@@ -689,7 +613,8 @@ extern "C" fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers
         WsLayout L = ws_layout(s, batches[i]);
         fv_status st = ensure_workspace(s, L.total);
         if (st) return st;
-        runs.push_back(GroupRun{s, states[i], batches[i], t[i], nullptr, err ? err[i] : nullptr, L, (char*)s->ws});
+        runs.push_back(GroupRun{s, states[i], batches[i], t[i], steps ? steps[i] : nullptr,
+                                err ? err[i] : nullptr, L, (char*)s->ws});
     }
     fv_status st = stream_enter(s0);
     if (st) return st;
@@ -704,6 +629,7 @@ extern "C" fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers
     for (int i = 0; i < n_groups; ++i) {
         key_push(key, solvers[i]); key_push(key, states[i]); key_push(key, batches[i]);
         key_push(key, t[i]); key_push(key, err ? err[i] : nullptr); key_push(key, solvers[i]->ws);
+        key_push(key, steps ? steps[i] : nullptr);
     }
     key_push(key, t_end); key_push(key, cfl); key_push(key, max_steps); key_push(key, s0->variant);
     key_push(key, chunk_steps(max_steps));
@@ -921,6 +847,74 @@ extern "C" fv_status fv_stats_accumulate(fv_stats* st, const double* state, int6
         st->count += nb;
     }
     return stream_leave(s);
+}
+
+static bool refinement_ratio(const fv_solver* f, const fv_solver* c, int32_t r[3])
+{
+    if (f->grid.dim != c->grid.dim || f->nf != c->nf || f->eq.kind != c->eq.kind) return false;
+    for (int k = 0; k < 3; ++k) {
+        if (c->grid.n[k] < 1 || f->grid.n[k] % c->grid.n[k] != 0) return false;
+        r[k] = (int32_t)(f->grid.n[k] / c->grid.n[k]);
+    }
+    return true;
+}
+
+extern "C" fv_status fv_stats_accumulate_diff(fv_stats* st, const double* fine,
+                                              const fv_solver* coarse, const double* coarse_state,
+                                              int64_t batch)
+{
+    if (!st || !fine || !coarse || !coarse_state) return fail(FV_EINVAL, "NULL argument");
+    if (batch < 1) return fail(FV_EINVAL, "batch must be >= 1");
+    if (st->max_h != 0) return fail(FV_ENOTSUP, "level differences take no structure functions (max_h = 0)");
+    fv_solver* s = const_cast<fv_solver*>(st->s);
+    DiffGeom geo{};
+    if (!refinement_ratio(s, coarse, geo.r))
+        return fail(FV_EINVAL, "coarse grid must divide the fine grid on every axis, same equation");
+    for (int k = 0; k < 3; ++k) {
+        geo.nf[k] = (int32_t)s->grid.n[k];
+        geo.nc[k] = (int32_t)coarse->grid.n[k];
+    }
+    HIP_TRY(hipSetDevice(s->device));
+    fv_status e = stream_enter(s);
+    if (e) return e;
+    const bool euler = s->eq.kind == FV_EQ_EULER;
+    const int64_t per_f = (int64_t)s->nf * s->cells, per_c = (int64_t)coarse->nf * coarse->cells;
+    for (int64_t b0 = 0; b0 < batch; b0 += 1024) {
+        const int32_t nb = (int32_t)std::min<int64_t>(1024, batch - b0);
+        launch_welford_diff(s->nf, euler, fine + b0 * per_f, coarse_state + b0 * per_c, geo, nb,
+                            st->count, st->mean, st->m2, s->stream);
+        HIP_TRY(hipGetLastError());
+        st->count += nb;
+    }
+    return stream_leave(s);
+}
+
+extern "C" fv_status fv_mlmc_combine(int32_t nlevels, const fv_stats* const* levels, double* out)
+{
+    if (nlevels < 1 || nlevels > kMaxLevels) return fail(FV_EINVAL, "nlevels must be in [1, 8]");
+    if (!levels || !out) return fail(FV_EINVAL, "NULL argument");
+    const fv_stats* fin = levels[nlevels - 1];
+    if (!fin) return fail(FV_EINVAL, "NULL level");
+    const fv_solver* sf = fin->s;
+    CombineArgs a{};
+    a.nlevels = nlevels;
+    a.nq = fin->nq;
+    for (int k = 0; k < 3; ++k) a.nfine[k] = (int32_t)sf->grid.n[k];
+    for (int l = 0; l < nlevels; ++l) {
+        const fv_stats* lv = levels[l];
+        if (!lv) return fail(FV_EINVAL, "NULL level");
+        if (lv->count < 1) return fail(FV_EINVAL, "a level has no samples");
+        if (!refinement_ratio(sf, lv->s, a.r[l])) return fail(FV_EINVAL, "levels must refine the finest grid");
+        a.mean[l] = lv->mean;
+        for (int k = 0; k < 3; ++k) a.n[l][k] = (int32_t)lv->s->grid.n[k];
+    }
+    fv_solver* s = const_cast<fv_solver*>(sf);
+    HIP_TRY(hipSetDevice(s->device));
+    for (int l = 0; l < nlevels; ++l) HIP_TRY(hipStreamSynchronize(levels[l]->s->stream));
+    launch_mlmc_combine(a, out, s->stream);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return FV_OK;
 }
 
 extern "C" fv_status fv_stats_read(const fv_stats* st, double* mean, double* var, double* s2_mean,

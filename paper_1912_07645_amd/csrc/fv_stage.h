@@ -7,11 +7,11 @@
 //      HBM into LDS; periodic axes wrap, transmissive axes clamp to the edge cell, so no
 //      padded copy exists in memory;
 //   2. faces: every face of the tile, of every axis, is reconstructed and its numerical flux
-//      computed exactly once. The faces of all axes form one list (x faces, then y, then z),
-//      dealt to the threads in order, with the face axis a run-time value; tile shapes are
+//      computed exactly once. The faces of all axes form one list (x faces, then y, then z,
+//      each axis padded to whole wavefronts), dealt to the threads in order; tile shapes are
 //      chosen so the list fills the workgroup's wavefronts evenly (e.g. 16 x 15 cells have
-//      511 faces for 2 x 256 lanes), so no wavefront does an extra pass for the "+1" row of
-//      faces that every tile has along each axis;
+//      255 + 256 faces for 2 x 256 lanes), so no wavefront does an extra pass for the "+1"
+//      row of faces that every tile has along each axis;
 //   3. divergence: each cell adds (F_+ - F_-) / dx_k in the order x, y, z (eq. 2.1);
 //   4. Runge--Kutta stage: U^(s) = U^n + beta ((U^(s-1) - U^n) + dt L(U^(s-1))), written to
 //      HBM; in the last stage the new state's wave speed is reduced across the workgroup
@@ -65,51 +65,70 @@ struct StageTile {
     static_assert(DIM >= 3 || BZ == 1, "2D tiles are flat");
 };
 
-// All faces of the tile into sf[q][face] (x faces, then y faces, then z faces).
+// One face with normal axis ND (compile-time): reconstruction from the LDS tile and the
+// numerical flux, stored into sf[q][f] when `store`.
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int ND>
+__device__ __forceinline__ void one_face(const double* su, double* sf, const Phys& ph, int l,
+                                         int f, bool store)
+{
+    using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    constexpr int NF = T::NF, G = T::G, PX = T::PX, PY = T::PY, PCELLS = T::PCELLS;
+    constexpr int NFACES = T::NFACES;
+    constexpr int GY = (DIM >= 2) ? G : 0, GZ = (DIM >= 3) ? G : 0;
+    constexpr int EX = BX + (ND == 0), EY = BY + (ND == 1);
+    constexpr int STRIDE = (ND == 0) ? 1 : ((ND == 1) ? PX : PX * PY);
+    const int fx = l % EX;
+    const int fy = (l / EX) % EY;
+    const int fz = l / (EX * EY);
+    // LDS index of the cell on the right of the face (the face is its "minus" side)
+    const int c = ((fz + GZ) * PY + (fy + GY)) * PX + (fx + G);
+    double UL[NF], UR[NF], F[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+        const double* s = su + q * PCELLS + c;
+        if (RECON == REC_FIRST) {
+            reconstruct<RECON>(0.0, s[-STRIDE], s[0], 0.0, UL[q], UR[q]);
+        } else {
+            reconstruct<RECON>(s[-2 * STRIDE], s[-STRIDE], s[0], s[STRIDE], UL[q], UR[q]);
+        }
+    }
+    numflux<DIM, EQ, FLUX>(UL, UR, ND, F, ph);
+    if (store) {
+#pragma unroll
+        for (int q = 0; q < NF; ++q) sf[q * NFACES + f] = F[q];
+    }
+}
+
+// All faces of the tile into sf[q][face] (x faces, then y faces, then z faces). Each axis's
+// list is padded to whole wavefronts, so the faces a wavefront takes in one pass share one
+// axis: the axis is wave-uniform and selects a compile-time face routine (padding lanes
+// recompute a valid face and store nothing).
 template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
 __device__ __forceinline__ void tile_faces(const double* su, double* sf, const Phys& ph)
 {
     using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
-    constexpr int NF = T::NF, G = T::G, PX = T::PX, PY = T::PY, PCELLS = T::PCELLS;
-    constexpr int NFX = T::NFX, NFY = T::NFY, NFACES = T::NFACES;
-    constexpr int GY = (DIM >= 2) ? G : 0, GZ = (DIM >= 3) ? G : 0;
-    for (int f = threadIdx.x; f < NFACES; f += NT) {
-        // decode (axis, face coordinates); each branch divides by compile-time constants
-        int nd, fx, fy, fz;
-        if (f < NFX) {
-            nd = 0;
-            fx = f % (BX + 1);
-            fy = (f / (BX + 1)) % BY;
-            fz = f / ((BX + 1) * BY);
-        } else if (DIM >= 2 && f < NFX + NFY) {
-            const int l = f - NFX;
-            nd = 1;
-            fx = l % BX;
-            fy = (l / BX) % (BY + 1);
-            fz = l / (BX * (BY + 1));
-        } else {
-            const int l = f - NFX - NFY;
-            nd = 2;
-            fx = l % BX;
-            fy = (l / BX) % BY;
-            fz = l / (BX * BY);
+    constexpr int NFX = T::NFX, NFY = T::NFY, NFZ = T::NFZ;
+    constexpr int PXN = (NFX + 63) / 64 * 64;
+    constexpr int PYN = (NFY + 63) / 64 * 64;
+    constexpr int PZN = (NFZ + 63) / 64 * 64;
+    constexpr int TOTAL = PXN + PYN + PZN;
+    for (int pf = threadIdx.x; pf < TOTAL; pf += NT) {
+        const int wave_first = __builtin_amdgcn_readfirstlane(pf);  // same axis for the wave
+        if (wave_first < PXN) {
+            const int l = pf;
+            const bool ok = l < NFX;
+            one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, 0>(su, sf, ph, ok ? l : NFX - 1, l, ok);
+        } else if (DIM >= 2 && wave_first < PXN + PYN) {
+            const int l = pf - PXN;
+            const bool ok = l < NFY;
+            one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, (DIM >= 2 ? 1 : 0)>(
+                su, sf, ph, ok ? l : NFY - 1, NFX + l, ok);
+        } else if (DIM >= 3) {
+            const int l = pf - PXN - PYN;
+            const bool ok = l < NFZ;
+            one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, (DIM >= 3 ? 2 : 0)>(
+                su, sf, ph, ok ? l : NFZ - 1, NFX + NFY + l, ok);
         }
-        // LDS index of the cell on the right of the face (the face is its "minus" side)
-        const int c = ((fz + GZ) * PY + (fy + GY)) * PX + (fx + G);
-        const int stride = (nd == 0) ? 1 : ((nd == 1) ? PX : PX * PY);
-        double UL[NF], UR[NF], F[NF];
-#pragma unroll
-        for (int q = 0; q < NF; ++q) {
-            const double* s = su + q * PCELLS + c;
-            if (RECON == REC_FIRST) {
-                reconstruct<RECON>(0.0, s[-stride], s[0], 0.0, UL[q], UR[q]);
-            } else {
-                reconstruct<RECON>(s[-2 * stride], s[-stride], s[0], s[stride], UL[q], UR[q]);
-            }
-        }
-        numflux<DIM, EQ, FLUX>(UL, UR, nd, F, ph);
-#pragma unroll
-        for (int q = 0; q < NF; ++q) sf[q * NFACES + f] = F[q];
     }
 }
 

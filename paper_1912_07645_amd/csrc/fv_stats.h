@@ -5,6 +5,29 @@
 
 namespace fvk {
 
+// Fine grid, coarse grid and their integer refinement ratio per axis.
+struct DiffGeom {
+    int32_t nf[3];
+    int32_t nc[3];
+    int32_t r[3];
+};
+
+constexpr int kMaxLevels = 8;
+
+struct CombineArgs {
+    const double* mean[kMaxLevels];  // [quantity][cells of level l]
+    int32_t n[kMaxLevels][3];        // grid of level l
+    int32_t r[kMaxLevels][3];        // finest / level l, per axis
+    int32_t nfine[3];
+    int32_t nlevels;
+    int32_t nq;
+};
+
+void launch_welford_diff(int nf, bool euler, const double* fine, const double* coarse,
+                         const DiffGeom& geo, int32_t batch, int64_t count0, double* mean,
+                         double* m2, hipStream_t s);
+void launch_mlmc_combine(const CombineArgs& a, double* out, hipStream_t s);
+
 int sf_blocks_per_field(int64_t cells);
 void launch_welford(int nf, bool euler, const double* state, int64_t cells, int32_t batch,
                     int64_t count0, double* mean, double* m2, hipStream_t s);

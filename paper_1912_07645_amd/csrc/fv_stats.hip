@@ -154,6 +154,106 @@ __global__ void sf_welford_kernel(const double* __restrict__ partial, int32_t nq
     s2m2[t] = s2;
 }
 
+// Multilevel Monte Carlo level differences: per fine cell, Welford over coupled samples of
+// x = q(u_fine) - q(u_coarse at the parent cell) (piecewise-constant prolongation).
+template <int NF, bool EULER>
+__global__ void __launch_bounds__(256)
+welford_diff_kernel(const double* __restrict__ fine, const double* __restrict__ coarse,
+                    DiffGeom geo, int32_t batch, int64_t count0, double* __restrict__ mean,
+                    double* __restrict__ m2)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t cells = (int64_t)geo.nf[0] * geo.nf[1] * geo.nf[2];
+    const int64_t ccells = (int64_t)geo.nc[0] * geo.nc[1] * geo.nc[2];
+    if (c >= cells) return;
+    const int32_t i = (int32_t)(c % geo.nf[0]);
+    const int32_t j = (int32_t)((c / geo.nf[0]) % geo.nf[1]);
+    const int32_t k = (int32_t)(c / ((int64_t)geo.nf[0] * geo.nf[1]));
+    const int64_t pc = ((int64_t)(k / geo.r[2]) * geo.nc[1] + (j / geo.r[1])) * geo.nc[0] + (i / geo.r[0]);
+    double mu[NF], s2[NF];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+        mu[q] = mean[q * cells + c];
+        s2[q] = m2[q * cells + c];
+    }
+    for (int32_t b = 0; b < batch; ++b) {
+        const double* Uf = fine + (int64_t)b * NF * cells + c;
+        const double* Uc = coarse + (int64_t)b * NF * ccells + pc;
+        double xf[NF], xc[NF];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            xf[q] = Uf[q * cells];
+            xc[q] = Uc[q * ccells];
+        }
+        if (EULER) {
+            const double irf = 1.0 / xf[0];
+            const double irc = 1.0 / xc[0];
+#pragma unroll
+            for (int q = 1; q < NF - 1; ++q) {
+                xf[q] = xf[q] * irf;
+                xc[q] = xc[q] * irc;
+            }
+        }
+        const double n = (double)(count0 + b + 1);
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const double x = xf[q] - xc[q];
+            const double delta = x - mu[q];
+            mu[q] = mu[q] + (delta / n);
+            s2[q] = s2[q] + (delta * (x - mu[q]));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+        mean[q * cells + c] = mu[q];
+        m2[q * cells + c] = s2[q];
+    }
+}
+
+// Multilevel estimate on the finest grid: out = sum_l P_{l->L} mean_l, levels in order.
+__global__ void mlmc_combine_kernel(const CombineArgs a, double* __restrict__ out)
+{
+    const int64_t cells = (int64_t)a.nfine[0] * a.nfine[1] * a.nfine[2];
+    const int64_t total = cells * a.nq;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = t / cells, c = t % cells;
+        const int32_t i = (int32_t)(c % a.nfine[0]);
+        const int32_t j = (int32_t)((c / a.nfine[0]) % a.nfine[1]);
+        const int32_t k = (int32_t)(c / ((int64_t)a.nfine[0] * a.nfine[1]));
+        double acc = 0.0;
+        for (int l = 0; l < a.nlevels; ++l) {
+            const int32_t* n = a.n[l];
+            const int32_t* r = a.r[l];
+            const int64_t lc = (int64_t)n[0] * n[1] * n[2];
+            const int64_t pc = ((int64_t)(k / r[2]) * n[1] + (j / r[1])) * n[0] + (i / r[0]);
+            const double v = a.mean[l][q * lc + pc];
+            acc = (l == 0) ? v : (acc + v);
+        }
+        out[t] = acc;
+    }
+}
+
+void launch_welford_diff(int nf, bool euler, const double* fine, const double* coarse,
+                         const DiffGeom& geo, int32_t batch, int64_t count0, double* mean,
+                         double* m2, hipStream_t s)
+{
+    const int64_t cells = (int64_t)geo.nf[0] * geo.nf[1] * geo.nf[2];
+    const unsigned nb = (unsigned)((cells + 255) / 256);
+#define FV_DIFF(NFV, E) hipLaunchKernelGGL((welford_diff_kernel<NFV, E>), dim3(nb), dim3(256), 0, s, \
+                                           fine, coarse, geo, batch, count0, mean, m2)
+    if (!euler) FV_DIFF(1, false);
+    else if (nf == 3) FV_DIFF(3, true);
+    else if (nf == 4) FV_DIFF(4, true);
+    else FV_DIFF(5, true);
+#undef FV_DIFF
+}
+
+void launch_mlmc_combine(const CombineArgs& a, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlmc_combine_kernel, dim3(1024), dim3(256), 0, s, a, out);
+}
+
 __global__ void variance_kernel(const double* __restrict__ m2, int64_t n, double count,
                                 double* __restrict__ var)
 {

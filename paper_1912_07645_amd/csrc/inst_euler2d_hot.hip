@@ -1,13 +1,12 @@
 // 2D Euler WENO3 + HLLC (the Kelvin--Helmholtz configuration): tile shapes for the tuner.
-// Each shape's face list fills its wavefronts almost exactly (faces / lanes per pass):
-// 16x15: 511/512, 20x12: 512/512, 32x15 on 512 threads: 1007/1024, 32x7: 487/512.
+// Each shape's face list, padded per axis to whole wavefronts, fills whole passes:
+// 16x15: 256 + 256 for 2 x 256 lanes, 32x15 on 512 threads: 512 + 512, 32x7: 256 + 256.
 #include "fv_registry.h"
 #include "fv_stage.h"
 
 namespace fvk {
 static const RegEntry kTable[] = {
     FV_ENTRY(2, EQ_EULER, REC_WENO3, FLUX_HLLC, 16, 15, 1, 256),
-    FV_ENTRY(2, EQ_EULER, REC_WENO3, FLUX_HLLC, 20, 12, 1, 256),
     FV_ENTRY(2, EQ_EULER, REC_WENO3, FLUX_HLLC, 32, 15, 1, 512),
     FV_ENTRY(2, EQ_EULER, REC_WENO3, FLUX_HLLC, 32, 7, 1, 256),
 };

@@ -56,7 +56,7 @@ def _load():
         "fv_advance": (i32, [vp, vp, i64, vp, dbl, dbl, i64, vp, vp]),
         "fv_evolve_fixed_dt": (i32, [vp, vp, i64, dbl, i64, dbl, vp]),
         "fv_evolve_multi": (i32, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), C.POINTER(vp),
-                                  dbl, dbl, i64, C.POINTER(vp)]),
+                                  dbl, dbl, i64, C.POINTER(vp), C.POINTER(vp)]),
         "fv_num_variants": (i32, [vp]),
         "fv_set_variant": (i32, [vp, i32]),
         "fv_get_tile": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
@@ -65,8 +65,16 @@ def _load():
         "fv_stats_accumulate": (i32, [vp, vp, i64]),
         "fv_stats_read": (i32, [vp, vp, vp, vp, vp, C.POINTER(i64)]),
         "fv_stats_reset": (i32, [vp]),
+        "fv_stats_accumulate_diff": (i32, [vp, vp, vp, vp, i64]),
+        "fv_mlmc_combine": (i32, [i32, C.POINTER(vp), vp]),
         "fv_stats_destroy": (i32, [vp]),
         "fv_check_arith": (i32, [vp, vp, vp, vp, i64]),
+        "fv_adjoint_create": (i32, [vp, i64, i64, dbl, i64, dbl, C.POINTER(vp)]),
+        "fv_adjoint_forward": (i32, [vp, vp, vp]),
+        "fv_adjoint_backward": (i32, [vp, vp, vp]),
+        "fv_adjoint_destroy": (i32, [vp]),
+        "fv_qoi_kinetic_energy": (i32, [vp, vp, i64, i64, i64, vp, vp, vp]),
+        "fv_line_vjp": (i32, [vp, vp, vp, vp, i32, i64, vp]),
         "fv_profile_enable": (i32, [vp, i32]),
         "fv_profile_read": (i32, [vp, C.POINTER(dbl), C.POINTER(i64)]),
         "fv_last_error": (C.c_char_p, []),
@@ -179,13 +187,16 @@ def fv_evolve_fixed_dt(solver, state, batch, dt, nsteps, cfl_bound, err=None) ->
     return st
 
 
-def fv_evolve_multi(solvers, states, batches, ts, t_end, cfl, max_steps, errs=None) -> int:
+def fv_evolve_multi(solvers, states, batches, ts, t_end, cfl, max_steps, steps=None,
+                    errs=None) -> int:
     n = len(solvers)
     A = C.c_void_p * n
     errs = errs if errs is not None else [None] * n
+    steps = steps if steps is not None else [None] * n
     st = lib.fv_evolve_multi(n, A(*solvers), A(*[ptr(s) for s in states]),
                              (C.c_int64 * n)(*[int(b) for b in batches]), A(*[ptr(t) for t in ts]),
-                             float(t_end), float(cfl), int(max_steps), A(*[ptr(e) for e in errs]))
+                             float(t_end), float(cfl), int(max_steps),
+                             A(*[ptr(k) for k in steps]), A(*[ptr(e) for e in errs]))
     if st in (FV_EINVAL, FV_ENOTSUP, FV_ENOMEM, FV_EDEVICE):
         check(st, "fv_evolve_multi")
     return st
@@ -228,6 +239,16 @@ def fv_stats_read(stats, mean=None, var=None, s2_mean=None, s2_var=None) -> int:
     return n.value
 
 
+def fv_stats_accumulate_diff(stats, fine, coarse_solver, coarse_state, batch) -> None:
+    check(lib.fv_stats_accumulate_diff(stats, ptr(fine), coarse_solver, ptr(coarse_state), int(batch)),
+          "fv_stats_accumulate_diff")
+
+
+def fv_mlmc_combine(levels, out) -> None:
+    n = len(levels)
+    check(lib.fv_mlmc_combine(n, (C.c_void_p * n)(*levels), ptr(out)), "fv_mlmc_combine")
+
+
 def fv_stats_reset(stats) -> None:
     check(lib.fv_stats_reset(stats), "fv_stats_reset")
 
@@ -238,6 +259,35 @@ def fv_stats_destroy(stats) -> None:
 
 def fv_check_arith(a, b, quot, root) -> None:
     check(lib.fv_check_arith(ptr(a), ptr(b), ptr(quot), ptr(root), a.numel()), "fv_check_arith")
+
+
+def fv_adjoint_create(solver, batch, nsteps, dt, every=0, cfl_bound=1.0) -> int:
+    h = C.c_void_p()
+    check(lib.fv_adjoint_create(solver, int(batch), int(nsteps), float(dt), int(every),
+                                float(cfl_bound), C.byref(h)), "fv_adjoint_create")
+    return h.value
+
+
+def fv_adjoint_forward(adj, state0, stateT) -> None:
+    check(lib.fv_adjoint_forward(adj, ptr(state0), ptr(stateT)), "fv_adjoint_forward")
+
+
+def fv_adjoint_backward(adj, dQ_dUT, dQ_dU0) -> None:
+    check(lib.fv_adjoint_backward(adj, ptr(dQ_dUT), ptr(dQ_dU0)), "fv_adjoint_backward")
+
+
+def fv_adjoint_destroy(adj) -> None:
+    check(lib.fv_adjoint_destroy(adj), "fv_adjoint_destroy")
+
+
+def fv_qoi_kinetic_energy(solver, state, batch, j0, j1, seed=None, Q=None, dQ_dU=None) -> None:
+    check(lib.fv_qoi_kinetic_energy(solver, ptr(state), int(batch), int(j0), int(j1), ptr(seed),
+                                    ptr(Q), ptr(dQ_dU)), "fv_qoi_kinetic_energy")
+
+
+def fv_line_vjp(solver, lambda0, dU_dline, dline_dtheta, ntheta, batch, out) -> None:
+    check(lib.fv_line_vjp(solver, ptr(lambda0), ptr(dU_dline), ptr(dline_dtheta), int(ntheta),
+                          int(batch), ptr(out)), "fv_line_vjp")
 
 
 def fv_profile_enable(solver, on: bool) -> None:

@@ -101,12 +101,20 @@ class Solver:
         return fv.fv_tune(self.handle, U, B, reps)
 
 
-def evolve_multi(solvers, states, ts, t_end, cfl, max_steps=10**9, errs=None) -> int:
+def mlmc_combine(levels) -> "torch.Tensor":
+    """sum_l P_{l->L} mean_l on the finest (last) level's grid (levels ordered coarse to fine)."""
+    fin = levels[-1].solver
+    out = torch.empty((fin.nf,) + fin.state_shape[1:], dtype=torch.float64, device=fin.device)
+    fv.fv_mlmc_combine([lv.handle for lv in levels], out)
+    return out
+
+
+def evolve_multi(solvers, states, ts, t_end, cfl, max_steps=10**9, steps=None, errs=None) -> int:
     """Evolve several grids (e.g. multilevel Monte Carlo levels) in shared launches."""
     for s, U in zip(solvers, states):
         s._prepare(s._check_state(U))
     return fv.fv_evolve_multi([s.handle for s in solvers], states, [U.shape[0] for U in states],
-                              ts, t_end, cfl, max_steps, errs)
+                              ts, t_end, cfl, max_steps, steps, errs)
 
 
 class Stats:
@@ -130,6 +138,14 @@ class Stats:
         B = self.solver._check_state(U)
         fv.fv_set_stream(self.solver.handle, torch.cuda.current_stream(self.solver.device).cuda_stream)
         fv.fv_stats_accumulate(self.handle, U, B)
+
+    def accumulate_diff(self, U_fine, coarse: Solver, U_coarse) -> None:
+        """Multilevel level difference: moments of q(u_fine) - P q(u_coarse)."""
+        B = self.solver._check_state(U_fine)
+        if coarse._check_state(U_coarse) != B:
+            raise ValueError("fine and coarse batches differ")
+        fv.fv_set_stream(self.solver.handle, torch.cuda.current_stream(self.solver.device).cuda_stream)
+        fv.fv_stats_accumulate_diff(self.handle, U_fine, coarse.handle, U_coarse, B)
 
     def reset(self) -> None:
         fv.fv_stats_reset(self.handle)

@@ -462,3 +462,68 @@ def test_structure_function_against_roll_formula():
     for h in (1, 2, 3):
         ref = sum(np.sum((np.roll(q, -h, axis=ax) - q) ** 2) for ax in (2, 1, 0)) / (3 * q.size)
         assert abs(O.structure_function(p, q, h) - ref) < 1e-13
+
+
+# --------------------------------------------------------------------------- multilevel MC
+
+def _upsample(a, r):
+    """Piecewise-constant prolongation of [..., ny, nx] by r on both axes."""
+    return np.repeat(np.repeat(a, r, axis=-1), r, axis=-2)
+
+
+def test_mlmc_level_statistics_against_numpy():
+    rng = np.random.default_rng(8)
+    pf = O.Problem(dim=2, n=(16, 16), eq="euler")
+    pc = O.Problem(dim=2, n=(8, 8), eq="euler")
+    B = 30
+    Uf = fi.random_smooth_state(5, (1, 16, 16), 2, batch=B)
+    Uc = fi.random_smooth_state(6, (1, 8, 8), 2, batch=B)
+    Uf = Uf * (1 + 0.01 * rng.standard_normal(Uf.shape))
+    lv = O.LevelStats(pf, pc)
+    lv.accumulate(Uf[:11], Uc[:11])
+    lv.accumulate(Uf[11:], Uc[11:])
+    qf = np.stack([O.quantities(pf, Uf[b]) for b in range(B)])
+    qc = np.stack([O.quantities(pc, Uc[b]) for b in range(B)])
+    x = qf - _upsample(qc, 2)
+    assert np.allclose(lv.mean, x.mean(axis=0), rtol=1e-13, atol=1e-15)
+    assert np.allclose(lv.variance(), x.var(axis=0), rtol=1e-10, atol=1e-16)
+
+
+def test_mlmc_one_level_is_plain_monte_carlo():
+    p = O.Problem(dim=2, n=(8, 8), eq="euler")
+    U = fi.random_smooth_state(2, (1, 8, 8), 2, batch=12)
+    lv = O.LevelStats(p)
+    lv.accumulate(U)
+    st = O.Stats(p)
+    st.accumulate(U)
+    assert same(O.mlmc_combine([lv]), st.mean)
+
+
+def test_mlmc_telescopes_to_finest_mean_with_shared_samples():
+    """With the same samples on every level, sum_l (mean q_l - mean P q_{l-1}) telescopes to
+    the plain mean of the finest level."""
+    B = 10
+    ps = [O.Problem(dim=2, n=(n, n), eq="euler") for n in (4, 8, 16)]
+    Us = [fi.random_smooth_state(11, (1, n, n), 2, batch=B) for n in (4, 8, 16)]
+    levels = [O.LevelStats(ps[0])]
+    levels[0].accumulate(Us[0])
+    for l in (1, 2):
+        lv = O.LevelStats(ps[l], ps[l - 1])
+        lv.accumulate(Us[l], Us[l - 1])
+        levels.append(lv)
+    est = O.mlmc_combine(levels)
+    fin = O.Stats(ps[2])
+    fin.accumulate(Us[2])
+    assert np.allclose(est, fin.mean, rtol=1e-13, atol=1e-14)
+
+
+def test_mlmc_combine_against_numpy_prolongation():
+    ps = [O.Problem(dim=2, n=(n, n), eq="euler") for n in (4, 8, 16)]
+    levels = []
+    for l, p in enumerate(ps):
+        lv = O.LevelStats(p)
+        lv.accumulate(fi.random_smooth_state(20 + l, (1, p.n[1], p.n[0]), 2, batch=3))
+        levels.append(lv)
+    est = O.mlmc_combine(levels)
+    ref = _upsample(levels[0].mean, 4) + _upsample(levels[1].mean, 2) + levels[2].mean
+    assert same(est, ref)
