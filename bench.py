@@ -58,6 +58,9 @@ WORKLOADS = {
                  flux="hll", recon="muscl_minmod", integrator="ssprk2", cfl=0.4, batch=64,
                  seed=1913, steps=1, warmup=1, cpu_steps=2, t_end=1.0,
                  ns=(64, 128, 256, 512), Ms=(4096, 1024, 256, 64)),
+    "adjoint": dict(name="adjoint_kh2d_256x256_x64_samples_muscl_rusanov_ssprk3_500_steps", dim=2,
+                    n=256, flux="rusanov", recon="muscl_minmod", integrator="ssprk3", cfl=0.4,
+                    batch=64, seed=1915, steps=1, warmup=1, cpu_steps=2, nsteps=500),
     "sod": dict(name="sod_1024_first_order_rusanov_forward_euler", dim=1, n=1024,
                 flux="rusanov", recon="first_order", integrator="forward_euler", cfl=0.45,
                 batch=1, seed=0, steps=1000, warmup=100, cpu_steps=1000),
@@ -183,6 +186,65 @@ def run_mlmc(a, w):
     print(json.dumps(out))
 
 
+def run_adjoint(a, w):
+    """Gradient of the band kinetic energy with respect to the 20 perturbation coefficients of
+    each of 64 samples (256^2, 500 fixed steps): the plain forward run, then the forward run
+    with sqrt(N) checkpoints plus the reverse sweep; reports the adjoint/forward cost ratio."""
+    import numpy as np
+    import torch
+    import fv_inputs as fi
+    from paper_1912_07645_amd import Solver
+    from paper_1912_07645_amd.adjoint import Adjoint, LineInitialDataQoI, band_rows
+
+    n, B, N = w["n"], w["batch"], w["nsteps"]
+    c, phi = fi.kh_coefficients(w["seed"], np.arange(B))
+    U0, D, E = fi.kh2d_state_and_jacobian(n, c, phi)
+    s = Solver(dim=2, n=(n, n), eq="euler", flux=w["flux"], recon=w["recon"],
+               integrator=w["integrator"], device="cuda:0")
+    dev = torch.device("cuda:0")
+    U0d, Dd, Ed = (torch.from_numpy(x).to(dev) for x in (U0, D, E))
+    outer = (0.5 + (1.4 * 2.5 / 1.0) ** 0.5) * n       # max speed of the unperturbed outer state
+    Ut = U0d[:1].clone()
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    k = torch.zeros(1, dtype=torch.int64, device=dev)
+    s.advance(Ut, t, 1e9, 1e-9, 1, k)   # dt of the first step = 1e-9 / M0: read M0 back
+    M0 = 1e-9 / float(t[0])
+    dt = w["cfl"] / M0
+    j0, j1 = band_rows(n)
+    K = a.steps if a.steps is not None else w["steps"]
+    W = a.warmup if a.warmup is not None else w["warmup"]
+    adj = Adjoint(s, B, N, dt, cfl_bound=0.6)
+    fwd, grad = [], []
+    for r in range(W + K):
+        U = U0d.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.evolve_fixed_dt(U, dt, N, 0.6)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        theta = torch.tensor(np.concatenate([c, phi], axis=1), device=dev, requires_grad=True)
+        Q = LineInitialDataQoI.apply(theta, U0d, Dd, Ed, adj, j0, j1)
+        Q.sum().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r >= W:
+            fwd.append(t1 - t0)
+            grad.append(t2 - t1)
+    tf, tg = sum(fwd) / len(fwd), sum(grad) / len(grad)
+    cells = n * n * B * N
+    out = {
+        "metric": "FP64 cell-updates/s", "value": cells / tg, "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": tg * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w["name"], "grid": [n, n], "samples": B, "time_steps": N,
+                   "dt": dt, "checkpoint_every": adj.every, "outer_state_speed_check": outer,
+                   "step": "one gradient evaluation (forward with checkpoints + reverse sweep)"},
+        "forward_ms": tf * 1e3, "gradient_ms": tg * 1e3, "adjoint_over_forward_cost": tg / tf,
+        "roofline": None,
+    }
+    return out
+
+
 def per_sample_rate(s, U, cfl, K, B1):
     """The same kernels with one sample per launch (the unbatched way), over B1 samples."""
     import torch
@@ -207,6 +269,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="kh2d", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="kh2d only: skip the short batched-MC and adjoint measurements")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--variant", type=int, default=None, help="tile variant (default: tuned)")
     ap.add_argument("--tune-cache", default=None,
@@ -225,14 +289,22 @@ def main():
     if a.workload == "mlmc":
         run_mlmc(a, WORKLOADS["mlmc"])
         return
+    if a.workload == "adjoint":
+        print(json.dumps(run_adjoint(a, WORKLOADS["adjoint"])))
+        return
 
+    out = measure(a, dict(WORKLOADS[a.workload]))
+    print(json.dumps(out))
+
+
+def measure(a, w, steps=None, warmup=None):
+    """Time K full steps of workload w; returns the JSON record."""
     import numpy as np
     import torch
     from paper_1912_07645_amd import Solver, fv
 
-    w = dict(WORKLOADS[a.workload])
-    K = a.steps if a.steps is not None else w["steps"]
-    W = a.warmup if a.warmup is not None else w["warmup"]
+    K = a.steps if a.steps is not None else (steps if steps is not None else w["steps"])
+    W = a.warmup if a.warmup is not None else (warmup if warmup is not None else w["warmup"])
     dev = torch.device("cuda:0")
     U0 = initial_state(w)
     bc = "transmissive" if w["dim"] == 1 else "periodic"
@@ -309,6 +381,19 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "hbm_frac_whole_step": bytes_step * K / el / 1e9 / HBM_PEAK_GBS,
     }
+    if a.workload == "kh2d" and not a.no_extras:
+        # the other two headline figures, measured briefly on their own configurations
+        ea = argparse.Namespace(steps=None, warmup=None, no_cpu=True, tune_cache=a.tune_cache,
+                                variant=None, workload="mc", no_extras=True)
+        mc = measure(ea, dict(WORKLOADS["mc"]), steps=20, warmup=2)
+        out["batched_mc"] = {k: mc[k] for k in (
+            "mc_sample_steps_per_s", "per_sample_launch_sample_steps_per_s",
+            "batched_speedup_over_per_sample_launches", "stats_ms_for_batch")}
+        out["batched_mc"]["config"] = mc["config"]["workload"]
+        adj = run_adjoint(argparse.Namespace(steps=1, warmup=1), WORKLOADS["adjoint"])
+        out["adjoint"] = {k: adj[k] for k in ("forward_ms", "gradient_ms",
+                                               "adjoint_over_forward_cost")}
+        out["adjoint"]["config"] = adj["config"]["workload"]
     if w["name"].startswith("kh2d_256x256_x1024"):
         from paper_1912_07645_amd import Stats
         out["mc_sample_steps_per_s"] = B * K / el
@@ -330,7 +415,7 @@ def main():
         out["stats_ms_for_batch"] = (time.perf_counter() - t0) * 1e3
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, U0, w["cpu_steps"])
-    print(json.dumps(out))
+    return out
 
 
 if __name__ == "__main__":

@@ -115,7 +115,7 @@ static WsLayout ws_layout(const fv_solver* s, int64_t batch)
     L.bad = take(sizeof(int32_t) * batch);
     L.err = take(sizeof(int32_t) * batch);
     L.t = take(sizeof(double) * batch);
-    L.count = take(sizeof(int32_t) * 4);
+    L.count = take(sizeof(int32_t) * (1 + kMaxGroups));
     L.total = off;
     return L;
 }
@@ -191,7 +191,7 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_count, sizeof(int32_t) * 4, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&s->host_count, sizeof(int32_t) * (1 + kMaxGroups), hipHostMallocDefault);
     if (e != hipSuccess) {
         fv_destroy(s);
         return fail(FV_EDEVICE, std::string("fv_create: ") + hipGetErrorString(e));
@@ -418,10 +418,35 @@ static int64_t chunk_steps(int64_t max_steps)
     return std::min<int64_t>(c, std::max<int64_t>(1, max_steps));
 }
 
-// Run the step loop of a plan until no sample is running.
-static fv_status run_steps(fv_solver* s0, StepPlan& p, int64_t max_steps, const std::vector<char>& key)
+// Step-control settings of a run (copied into every plan).
+struct CtrlParams {
+    int32_t fixed, limit_is_error;
+    double t_end, cfl, fixed_dt, cfl_bound;
+    int64_t max_steps;
+};
+
+static void apply_params(StepPlan& p, const CtrlParams& c)
+{
+    p.ctrl.fixed = c.fixed;
+    p.ctrl.limit_is_error = c.limit_is_error;
+    p.ctrl.t_end = c.t_end;
+    p.ctrl.cfl = c.cfl;
+    p.ctrl.fixed_dt = c.fixed_dt;
+    p.ctrl.cfl_bound = c.cfl_bound;
+    p.ctrl.max_steps = c.max_steps;
+}
+
+// Run the step loop until no sample is running. When a group (a grid of a multi-group run)
+// has no running sample left, it is dropped from the launches and the graph is captured
+// again, so finished coarse levels stop costing launch slots.
+static fv_status run_steps(fv_solver* s0, std::vector<GroupRun> runs, const CtrlParams& cp,
+                           const std::vector<char>& key0)
 {
     hipStream_t st = s0->stream;
+    const int64_t max_steps = cp.max_steps;
+    StepPlan p = make_plan(runs);
+    apply_params(p, cp);
+    int32_t* counts_dev = p.ctrl.n_running;
     launch_ctrl_reset(p.ctrl, st);
     p.kern->speed(p.speed, st);
     launch_ctrl_begin(p.ctrl, st);
@@ -438,27 +463,48 @@ static fv_status run_steps(fv_solver* s0, StepPlan& p, int64_t max_steps, const 
             s0->prof_ev.push_back(e);
         }
     }
-    if (use_graph && (s0->graph.key != key || !s0->graph.exec)) {
-        drop_graph(s0);
-        hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        for (int64_t i = 0; i < chunk; ++i) enqueue_step(p, st);
-        hipError_t e = hipStreamEndCapture(st, &g);
-        if (e != hipSuccess) return fail(FV_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-        e = hipGraphInstantiate(&s0->graph.exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        if (e != hipSuccess) return fail(FV_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-        s0->graph.key = key;
-    }
-    // Each round advances every running sample by up to `chunk` steps (a captured graph),
-    // or by the remaining max_steps % chunk steps (enqueued directly) once fewer than
-    // `chunk` remain, so a run limited by max_steps launches exactly max_steps steps. A
-    // sample stops at t_end, on an error or at max_steps; after max_steps steps none runs.
-    HIP_TRY(hipMemcpyAsync(s0->host_count, p.ctrl.n_running, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (*s0->host_count == 0) return FV_OK;
+    std::vector<char> key = key0;
+    auto read_counts = [&]() -> fv_status {
+        HIP_TRY(hipMemcpyAsync(s0->host_count, counts_dev, sizeof(int32_t) * (1 + runs.size()),
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return FV_OK;
+    };
+    fv_status e = read_counts();
+    if (e) return e;
+    if (s0->host_count[0] == 0) return FV_OK;
     int64_t done = 0;
     while (done < max_steps) {
+        // drop groups that have finished (multi-group runs only)
+        if (runs.size() > 1) {
+            std::vector<GroupRun> keep;
+            for (size_t i = 0; i < runs.size(); ++i)
+                if (s0->host_count[1 + i] > 0) keep.push_back(runs[i]);
+            if (keep.size() != runs.size()) {
+                runs = keep;
+                p = make_plan(runs);
+                apply_params(p, cp);
+                p.ctrl.n_running = counts_dev;
+                drop_graph(s0);
+                key.push_back((char)runs.size());
+            }
+        }
+        if (use_graph && (s0->graph.key != key || !s0->graph.exec)) {
+            drop_graph(s0);
+            hipGraph_t g = nullptr;
+            HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int64_t i = 0; i < chunk; ++i) enqueue_step(p, st);
+            hipError_t ce = hipStreamEndCapture(st, &g);
+            if (ce != hipSuccess) return fail(FV_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+            ce = hipGraphInstantiate(&s0->graph.exec, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ce != hipSuccess) return fail(FV_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ce));
+            s0->graph.key = key;
+        }
+        // Each round advances every running sample by up to `chunk` steps (a captured graph),
+        // or by the remaining max_steps % chunk steps (enqueued directly) once fewer than
+        // `chunk` remain, so a run limited by max_steps launches exactly max_steps steps. A
+        // sample stops at t_end, on an error or at max_steps; after max_steps steps none runs.
         const int64_t n = std::min<int64_t>(chunk, std::max<int64_t>(1, max_steps - done));
         if (use_graph && n == chunk) {
             HIP_TRY(hipGraphLaunch(s0->graph.exec, st));
@@ -468,8 +514,8 @@ static fv_status run_steps(fv_solver* s0, StepPlan& p, int64_t max_steps, const 
             HIP_TRY(hipGetLastError());
         }
         done += n;
-        HIP_TRY(hipMemcpyAsync(s0->host_count, p.ctrl.n_running, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
+        e = read_counts();
+        if (e) return e;
         if (profile) {
             for (size_t i = 0; i < nst * (size_t)n; ++i) {
                 float ms = 0.0f;
@@ -478,7 +524,7 @@ static fv_status run_steps(fv_solver* s0, StepPlan& p, int64_t max_steps, const 
                 s0->prof_stage_launches += 1;
             }
         }
-        if (*s0->host_count == 0) return FV_OK;
+        if (s0->host_count[0] == 0) return FV_OK;
     }
     return fail(FV_EDEVICE, "step loop did not terminate");
 }
@@ -537,14 +583,7 @@ static fv_status evolve_common(fv_solver* s, double* state, int64_t batch, doubl
     if (st) return st;
 
     std::vector<GroupRun> runs{GroupRun{s, state, batch, fixed ? nullptr : t, steps, err, L, (char*)s->ws}};
-    StepPlan plan = make_plan(runs);
-    plan.ctrl.fixed = fixed;
-    plan.ctrl.limit_is_error = limit_is_error;
-    plan.ctrl.t_end = t_end;
-    plan.ctrl.cfl = cfl;
-    plan.ctrl.fixed_dt = fixed_dt;
-    plan.ctrl.cfl_bound = cfl_bound;
-    plan.ctrl.max_steps = max_steps;
+    const CtrlParams cp{fixed ? 1 : 0, limit_is_error ? 1 : 0, t_end, cfl, fixed_dt, cfl_bound, max_steps};
 
     std::vector<char> key;
     key_push(key, state); key_push(key, batch); key_push(key, t); key_push(key, steps);
@@ -553,10 +592,10 @@ static fv_status evolve_common(fv_solver* s, double* state, int64_t batch, doubl
     key_push(key, cfl_bound); key_push(key, s->ws); key_push(key, s->variant);
     key_push(key, chunk_steps(max_steps));
 
-    st = run_steps(s, plan, max_steps, key);
+    st = run_steps(s, runs, cp, key);
     if (st) return st;
     fv_status result = FV_OK;
-    st = first_error(s, plan.ctrl.g[0].err, batch, &result);
+    st = first_error(s, make_ctrl(runs[0]).err, batch, &result);
     if (st) return st;
     st = stream_leave(s);
     if (st) return st;
@@ -618,12 +657,7 @@ extern "C" fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers
     }
     fv_status st = stream_enter(s0);
     if (st) return st;
-    StepPlan plan = make_plan(runs);
-    plan.ctrl.fixed = 0;
-    plan.ctrl.limit_is_error = 1;
-    plan.ctrl.t_end = t_end;
-    plan.ctrl.cfl = cfl;
-    plan.ctrl.max_steps = max_steps;
+    const CtrlParams cp{0, 1, t_end, cfl, 0.0, 0.0, max_steps};
     std::vector<char> key;
     key_push(key, n_groups);
     for (int i = 0; i < n_groups; ++i) {
@@ -633,11 +667,11 @@ extern "C" fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers
     }
     key_push(key, t_end); key_push(key, cfl); key_push(key, max_steps); key_push(key, s0->variant);
     key_push(key, chunk_steps(max_steps));
-    st = run_steps(s0, plan, max_steps, key);
+    st = run_steps(s0, runs, cp, key);
     if (st) return st;
     fv_status result = FV_OK;
     for (int i = 0; i < n_groups && result == FV_OK; ++i) {
-        st = first_error(s0, plan.ctrl.g[i].err, batches[i], &result);
+        st = first_error(s0, make_ctrl(runs[i]).err, batches[i], &result);
         if (st) return st;
     }
     st = stream_leave(s0);

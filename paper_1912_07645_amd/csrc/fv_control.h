@@ -27,7 +27,7 @@ struct CtrlArgs {
     double fixed_dt;
     double cfl_bound;
     int64_t max_steps;
-    int32_t* n_running;      // out: samples taking the step just decided
+    int32_t* n_running;      // out: [0] samples taking the step just decided, [1 + g] per group
 };
 
 struct CopyGroup {

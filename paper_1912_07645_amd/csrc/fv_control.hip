@@ -29,12 +29,12 @@ __global__ void ctrl_reset_kernel(const CtrlArgs a)
 // samples still running into *n_running. Launched with one workgroup.
 __global__ void __launch_bounds__(1024) ctrl_begin_kernel(const CtrlArgs a)
 {
-    __shared__ int count;
-    if (threadIdx.x == 0) count = 0;
+    __shared__ int count[kMaxGroups];
+    if (threadIdx.x < kMaxGroups) count[threadIdx.x] = 0;
     __syncthreads();
-    int mine = 0;
     for (int gi = 0; gi < a.ngroups; ++gi) {
         const CtrlGroup& g = a.g[gi];
+        int mine = 0;
         for (int b = threadIdx.x; b < g.batch; b += blockDim.x) {
             if (!g.running[b]) { g.active[b] = 0; continue; }
             int stop = 0;
@@ -84,10 +84,17 @@ __global__ void __launch_bounds__(1024) ctrl_begin_kernel(const CtrlArgs a)
             g.bad[b] = 0;
             mine += 1;
         }
+        if (mine) atomicAdd(&count[gi], mine);
     }
-    if (mine) atomicAdd(&count, mine);
     __syncthreads();
-    if (threadIdx.x == 0) *a.n_running = count;
+    if (threadIdx.x == 0) {
+        int total = 0;
+        for (int gi = 0; gi < a.ngroups; ++gi) {
+            total += count[gi];
+            a.n_running[1 + gi] = count[gi];
+        }
+        a.n_running[0] = total;
+    }
 }
 
 // Forward Euler has a single stage that cannot update in place (neighbours read the old

@@ -211,8 +211,23 @@ __device__ __forceinline__ void reconstruct(double a, double b, double c, double
         uL = b + (0.5 * minmod(b - a, c - b));
         uR = c - (0.5 * minmod(c - b, d - c));
     } else {
-        uL = weno3(a, b, c);
-        uR = weno3(d, c, b);
+        // uL = weno3(a, b, c), uR = weno3(d, c, b). Both use the indicator of (b, c) and the
+        // candidate (b + c)/2: (b - c)^2 equals (c - b)^2 and b + c equals c + b bit for bit,
+        // so each is computed once.
+        const double dbc = c - b;
+        double tbc = 1e-6 + (dbc * dbc);
+        tbc = tbc * tbc;
+        const double q0 = 0.5 * (b + c);
+        const double dab = b - a;
+        double tab = 1e-6 + (dab * dab);
+        tab = tab * tab;
+        const double q1L = (1.5 * b) - (0.5 * a);
+        uL = (((2.0 * tab) * q0) + (tbc * q1L)) / ((2.0 * tab) + tbc);
+        const double ddc = c - d;
+        double tdc = 1e-6 + (ddc * ddc);
+        tdc = tdc * tdc;
+        const double q1R = (1.5 * c) - (0.5 * d);
+        uR = (((2.0 * tdc) * q0) + (tbc * q1R)) / ((2.0 * tdc) + tbc);
     }
 }
 

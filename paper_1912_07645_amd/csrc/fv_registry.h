@@ -28,6 +28,8 @@ FV_DECLARE_UNIT(unit_scalar3d)
 // Helpers for the instantiation units.
 #define FV_ENTRY(D, E, R, F, X, Y, Z, NT) \
     RegEntry{D, E, R, F, make_stage_kernel<D, E, R, F, X, Y, Z, NT>()}
+#define FV_ENTRY_H(D, E, R, F, X, Y, Z, NT, H) \
+    RegEntry{D, E, R, F, make_stage_kernel<D, E, R, F, X, Y, Z, NT, H>()}
 
 #define FV_ALL_RF(D, E, X, Y, Z, NT)                                                          \
     FV_ENTRY(D, E, REC_FIRST, FLUX_RUSANOV, X, Y, Z, NT), FV_ENTRY(D, E, REC_FIRST, FLUX_HLL, X, Y, Z, NT), \

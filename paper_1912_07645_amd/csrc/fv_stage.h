@@ -28,11 +28,19 @@ struct Ghost {
     static constexpr int value = (RECON == REC_FIRST) ? 1 : 2;
 };
 
+// Ghost-cell index map: periodic wrap or transmissive clamp. Tile loads ask for indices in
+// [-G, n + B + G); a single add or subtract covers them unless the grid is smaller than the
+// tile plus its halo, where the remainder is taken.
 __device__ __forceinline__ int32_t wrap_index(int32_t i, int32_t n, int32_t bc)
 {
     if (bc == BC_PERIODIC) {
-        int32_t r = i % n;
-        return r < 0 ? r + n : r;
+        if (i < 0) i += n;
+        else if (i >= n) i -= n;
+        if ((uint32_t)i >= (uint32_t)n) {
+            i %= n;
+            if (i < 0) i += n;
+        }
+        return i;
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
@@ -66,10 +74,9 @@ struct StageTile {
 };
 
 // One face with normal axis ND (compile-time): reconstruction from the LDS tile and the
-// numerical flux, stored into sf[q][f] when `store`.
+// numerical flux into F.
 template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int ND>
-__device__ __forceinline__ void one_face(const double* su, double* sf, const Phys& ph, int l,
-                                         int f, bool store)
+__device__ __forceinline__ void one_face(const double* su, const Phys& ph, int l, double* F)
 {
     using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
     constexpr int NF = T::NF, G = T::G, PX = T::PX, PY = T::PY, PCELLS = T::PCELLS;
@@ -82,7 +89,7 @@ __device__ __forceinline__ void one_face(const double* su, double* sf, const Phy
     const int fz = l / (EX * EY);
     // LDS index of the cell on the right of the face (the face is its "minus" side)
     const int c = ((fz + GZ) * PY + (fy + GY)) * PX + (fx + G);
-    double UL[NF], UR[NF], F[NF];
+    double UL[NF], UR[NF];
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
         const double* s = su + q * PCELLS + c;
@@ -93,41 +100,85 @@ __device__ __forceinline__ void one_face(const double* su, double* sf, const Phy
         }
     }
     numflux<DIM, EQ, FLUX>(UL, UR, ND, F, ph);
-    if (store) {
-#pragma unroll
-        for (int q = 0; q < NF; ++q) sf[q * NFACES + f] = F[q];
+}
+
+// Padded face list: each axis's faces rounded up to whole wavefronts, so the faces a
+// wavefront takes in one pass share one axis (wave-uniform, a compile-time face routine).
+template <int DIM, int EQ, int RECON, int BX, int BY, int BZ, int NT>
+struct FaceList {
+    using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    static constexpr int PXN = (T::NFX + 63) / 64 * 64;
+    static constexpr int PYN = (T::NFY + 63) / 64 * 64;
+    static constexpr int PZN = (T::NFZ + 63) / 64 * 64;
+    static constexpr int TOTAL = PXN + PYN + PZN;
+    static constexpr int FPT = (TOTAL + NT - 1) / NT;   // faces per thread
+};
+
+// Face pf of the padded list: F gets its flux, *slot its index in the unpadded list sf[q][f]
+// (-1 for padding; padding lanes recompute a valid face and store nothing).
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
+__device__ __forceinline__ void list_face(const double* su, const Phys& ph, int pf, double* F,
+                                          int* slot)
+{
+    using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    using L = FaceList<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    constexpr int NFX = T::NFX, NFY = T::NFY, NFZ = T::NFZ;
+    const int wave_first = __builtin_amdgcn_readfirstlane(pf);  // same axis for the wave
+    if (wave_first < L::PXN) {
+        const int l = pf;
+        const bool ok = l < NFX;
+        one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, 0>(su, ph, ok ? l : NFX - 1, F);
+        *slot = ok ? l : -1;
+    } else if (DIM >= 2 && wave_first < L::PXN + L::PYN) {
+        const int l = pf - L::PXN;
+        const bool ok = l < NFY;
+        one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, (DIM >= 2 ? 1 : 0)>(su, ph, ok ? l : NFY - 1, F);
+        *slot = ok ? NFX + l : -1;
+    } else {
+        const int l = pf - L::PXN - L::PYN;
+        const bool ok = DIM >= 3 && l < NFZ;
+        one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, (DIM >= 3 ? 2 : 0)>(su, ph, ok ? l : (NFZ > 0 ? NFZ - 1 : 0), F);
+        *slot = ok ? NFX + NFY + l : -1;
     }
 }
 
-// All faces of the tile into sf[q][face] (x faces, then y faces, then z faces). Each axis's
-// list is padded to whole wavefronts, so the faces a wavefront takes in one pass share one
-// axis: the axis is wave-uniform and selects a compile-time face routine (padding lanes
-// recompute a valid face and store nothing).
-template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
+// All faces of the tile into sf[q][face] (x faces, then y faces, then z faces).
+// HOLD = 0: each flux goes to its own LDS face buffer as soon as it is computed.
+// HOLD = 1: each thread keeps its fluxes in registers until every thread has finished
+// reading the state tile, then they are written over it (sf aliases su): the workgroup
+// needs max(state tile, faces) of LDS instead of their sum, so more workgroups fit a CU.
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD>
 __device__ __forceinline__ void tile_faces(const double* su, double* sf, const Phys& ph)
 {
     using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
-    constexpr int NFX = T::NFX, NFY = T::NFY, NFZ = T::NFZ;
-    constexpr int PXN = (NFX + 63) / 64 * 64;
-    constexpr int PYN = (NFY + 63) / 64 * 64;
-    constexpr int PZN = (NFZ + 63) / 64 * 64;
-    constexpr int TOTAL = PXN + PYN + PZN;
-    for (int pf = threadIdx.x; pf < TOTAL; pf += NT) {
-        const int wave_first = __builtin_amdgcn_readfirstlane(pf);  // same axis for the wave
-        if (wave_first < PXN) {
-            const int l = pf;
-            const bool ok = l < NFX;
-            one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, 0>(su, sf, ph, ok ? l : NFX - 1, l, ok);
-        } else if (DIM >= 2 && wave_first < PXN + PYN) {
-            const int l = pf - PXN;
-            const bool ok = l < NFY;
-            one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, (DIM >= 2 ? 1 : 0)>(
-                su, sf, ph, ok ? l : NFY - 1, NFX + l, ok);
-        } else if (DIM >= 3) {
-            const int l = pf - PXN - PYN;
-            const bool ok = l < NFZ;
-            one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, (DIM >= 3 ? 2 : 0)>(
-                su, sf, ph, ok ? l : NFZ - 1, NFX + NFY + l, ok);
+    using L = FaceList<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    constexpr int NF = T::NF, NFACES = T::NFACES;
+    if constexpr (!HOLD) {
+        for (int pf = threadIdx.x; pf < L::TOTAL; pf += NT) {
+            double F[NF];
+            int slot;
+            list_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT>(su, ph, pf, F, &slot);
+            if (slot >= 0) {
+#pragma unroll
+                for (int q = 0; q < NF; ++q) sf[q * NFACES + slot] = F[q];
+            }
+        }
+    } else {
+        double F[L::FPT][NF];
+        int slot[L::FPT];
+#pragma unroll
+        for (int k = 0; k < L::FPT; ++k) {
+            const int pf = threadIdx.x + k * NT;
+            slot[k] = -1;
+            if (pf < L::TOTAL) list_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT>(su, ph, pf, F[k], &slot[k]);
+        }
+        __syncthreads();   // the state tile is dead from here on
+#pragma unroll
+        for (int k = 0; k < L::FPT; ++k) {
+            if (slot[k] >= 0) {
+#pragma unroll
+                for (int q = 0; q < NF; ++q) sf[q * NFACES + slot[k]] = F[k][q];
+            }
         }
     }
 }
@@ -170,8 +221,8 @@ __device__ __forceinline__ int find_group(const Group* g, int ngroups, int64_t b
     return gi;
 }
 
-template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
-__global__ void __launch_bounds__(NT)
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(HOLD ? 6 : 1, 8)))
 stage_kernel(const StageArgs args)
 {
     using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
@@ -179,8 +230,11 @@ stage_kernel(const StageArgs args)
     constexpr int PCELLS = T::PCELLS, CPT = T::CPT, CELLS = T::CELLS;
     constexpr int NFX = T::NFX, NFY = T::NFY, NFACES = T::NFACES;
     constexpr int GY = (DIM >= 2) ? G : 0, GZ = (DIM >= 3) ? G : 0;
-    __shared__ double su[NF * PCELLS];
-    __shared__ double sf[NF * NFACES];
+    constexpr int SU = NF * PCELLS, SF = NF * NFACES;
+    constexpr int LDS = HOLD ? (SU > SF ? SU : SF) : SU + SF;
+    __shared__ double lds[LDS];
+    double* su = lds;
+    double* sf = HOLD ? lds : lds + SU;
 
     const int64_t blk = xcd_remap(blockIdx.x, args.nblocks);
     const int gi = find_group(args.g, args.ngroups, blk);
@@ -213,7 +267,7 @@ stage_kernel(const StageArgs args)
     __syncthreads();
 
     // 2. every face of the tile, once
-    tile_faces<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT>(su, sf, g.ph);
+    tile_faces<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, HOLD>(su, sf, g.ph);
     __syncthreads();
 
     // 3 + 4. divergence and Runge--Kutta stage combination
@@ -245,7 +299,7 @@ stage_kernel(const StageArgs args)
             if (DIM >= 2) acc = acc + ((F[fym + BX] - F[fym]) * g.ph.inv_dx[1]);
             if (DIM >= 3) acc = acc + ((F[fzm + BX * BY] - F[fzm]) * g.ph.inv_dx[2]);
             const double rhs = -acc;
-            const double up = su[q * PCELLS + lc];
+            const double up = HOLD ? src[q * g.cells + gidx] : su[q * PCELLS + lc];
             const double u0 = args.use_un ? un[q * g.cells + gidx] : up;
             out[q] = u0 + (beta * ((up - u0) + (dt * rhs)));
             dst[q * g.cells + gidx] = out[q];
@@ -289,10 +343,10 @@ speed_kernel(const SpeedArgs args, int cells_per_block)
     block_merge_speed<kThreads>(m, bad, &g.mbits[sample], &g.bad[sample]);
 }
 
-template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD>
 void launch_stage(const StageArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((stage_kernel<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT>),
+    hipLaunchKernelGGL((stage_kernel<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, HOLD>),
                        dim3((unsigned)a.nblocks), dim3(NT), 0, s, a);
 }
 
@@ -305,11 +359,11 @@ void launch_speed(const SpeedArgs& a, hipStream_t s)
                        kSpeedCellsPerBlock);
 }
 
-template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT>
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD = 1>
 constexpr StageKernel make_stage_kernel()
 {
-    return StageKernel{&launch_stage<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT>, &launch_speed<DIM, EQ>,
-                       BX, BY, BZ, kSpeedCellsPerBlock};
+    return StageKernel{&launch_stage<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, HOLD>,
+                       &launch_speed<DIM, EQ>, BX, BY, BZ, kSpeedCellsPerBlock};
 }
 
 }  // namespace fvk
