@@ -30,7 +30,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, 8 TB/s
-FP64_VALU_TFLOPS = 78.6     # MI355X FP64 vector (FMA = 2 flops)
+# FP64 vector peak without FMA: 256 CUs x 64 FP64 lanes per clock x 2.4 GHz = 39.3e12 ops/s
+# (the published 78.6 TFLOP/s counts an FMA as 2 flops; the arithmetic contract forbids FMA
+# contraction, so every operation is one lane-op)
+FP64_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+
+# FP64 lane-operations the arithmetic contract needs, with each face counted once: every
+# + - x and comparison/select counts 1, a correctly rounded division 10 and a square root 14
+# (the lengths of their gfx950 expansions). Derivation in the design notes.
+WENO3_PER_COMPONENT = 50        # both face values of one component (shared indicator)
+EULER_PRIM = {1: 31, 2: 34, 3: 37}            # primitives of one face state
+EULER_FLUX = {1: 4, 2: 5, 3: 6}                # physical flux of one face state
+HLLC = {1: 81, 2: 91, 3: 101}                  # wave speeds, contact, star state, selects
+DIVERGENCE_RK = {1: 3 + 5, 2: 6 + 5, 3: 9 + 5}  # per component: flux difference sum, stage
+CFL_CELL = {1: 45, 2: 47, 3: 55}              # per cell, last stage only
+
+
+def lane_ops_per_cell_stage(dim: int, integrator: str) -> float:
+    """WENO3 + HLLC Euler: algorithmic FP64 lane-ops per cell per Runge--Kutta stage."""
+    nf = dim + 2
+    face = nf * WENO3_PER_COMPONENT + 2 * (EULER_PRIM[dim] + EULER_FLUX[dim]) + HLLC[dim]
+    stages = {"forward_euler": 1, "ssprk2": 2, "ssprk3": 3}[integrator]
+    return dim * face + nf * DIVERGENCE_RK[dim] + CFL_CELL[dim] / stages
 
 # Algorithmic HBM bytes per cell per full step (streaming minimum: each stage reads its
 # input state once, stages >= 2 re-read U^n, every stage writes its output once; halos and
@@ -357,6 +378,24 @@ def measure(a, w, steps=None, warmup=None):
     avg_launch_s = stage_ms * 1e-3 / launches
     bytes_per_launch = bytes_step / nstages
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_per_launch,
+           "traffic": measured_traffic(a.workload)}
+    if w["recon"] == "weno3" and w["flux"] == "hllc":
+        ops_launch = lane_ops_per_cell_stage(w["dim"], w["integrator"]) * cells * B
+        alu_tops = ops_launch / avg_launch_s / 1e12
+        roof = {"bound": "alu", "achieved": alu_tops, "peak": FP64_LANE_OPS_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": alu_tops * 1e12 / FP64_LANE_OPS_PEAK,
+                "traffic": hbm["traffic"], "kernel": "stage_kernel",
+                "avg_launch_us": avg_launch_s * 1e6,
+                "algorithmic_fp64_ops_per_launch": ops_launch,
+                "fp64_ops_per_cell_stage": lane_ops_per_cell_stage(w["dim"], w["integrator"]),
+                "hbm": hbm}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": hbm["traffic"],
+                "kernel": "stage_kernel", "avg_launch_us": avg_launch_s * 1e6,
+                "algorithmic_bytes_per_launch": bytes_per_launch}
 
     out = {
         "metric": "FP64 cell-updates/s",
@@ -374,11 +413,7 @@ def measure(a, w, steps=None, warmup=None):
         "config": {"workload": w["name"], "grid": [w["n"]] * w["dim"], "samples": B,
                    "cells_per_sample": cells, "cfl": w["cfl"], "seed": w["seed"],
                    "tile": list(tile), "tuned_variant": tuned},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(a.workload),
-                     "kernel": "stage_kernel", "avg_launch_us": avg_launch_s * 1e6,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "roofline": roof,
         "hbm_frac_whole_step": bytes_step * K / el / 1e9 / HBM_PEAK_GBS,
     }
     if a.workload == "kh2d" and not a.no_extras:
