@@ -175,6 +175,9 @@ def run_mlmc(a, w):
     K = a.steps if a.steps is not None else w["steps"]
     W = a.warmup if a.warmup is not None else w["warmup"]
     dev_groups = [torch.from_numpy(g).to("cuda:0") for g in groups]
+    tuned = run.tune(dev_groups, w["cfl"]) if a.variant is None else a.variant
+    for s in run.solvers:
+        s.set_variant(tuned)
     times, cell_updates = [], 0
     steps_per_grid = None
     for r in range(W + K):
@@ -200,7 +203,8 @@ def run_mlmc(a, w):
                    "samples_per_grid": [int(g.shape[0]) for g in groups],
                    "sample_steps_per_grid": steps_per_grid, "t_end": w["t_end"],
                    "cfl": w["cfl"], "seed": w["seed"],
-                   "step": "one whole multilevel run (all levels to T, statistics, estimate)"},
+                   "step": "one whole multilevel run (all levels to T, statistics, estimate)",
+                   "tile": list(run.solvers[0].tile()[0]), "tuned_variant": tuned},
         "mlmc_runs_per_s": 1.0 / el,
         "roofline": None,
     }

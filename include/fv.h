@@ -85,7 +85,8 @@ typedef struct fv_adjoint fv_adjoint; /* opaque, library-owned */
 /* Create a solver for one grid, equation and scheme (Section 2.1: numerical flux, face
  * reconstruction, SSP Runge--Kutta stepper). flux, recon, integrator take the enum values
  * above. *out receives the handle. FV_ENOTSUP for HLLC with a scalar equation; FV_EINVAL
- * for any malformed grid or enum; FV_EDEVICE if no gfx950 device is current. */
+ * for any malformed grid or enum, or a grid of more than 2^31 - 1 cells; FV_EDEVICE if no
+ * gfx950 device is current. */
 fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32_t flux, int32_t recon,
                     int32_t integrator, fv_solver** out);
 

@@ -21,6 +21,7 @@
 #include "fv_common.h"
 #include "fv_control.h"
 #include "fv_host.h"
+#include <climits>
 #include "fv_registry.h"
 #include "fv_stats.h"
 
@@ -145,7 +146,8 @@ static fv_status validate_grid(const fv_grid* g)
             return fail(FV_EINVAL, "grid.bc must be periodic or transmissive");
         cells *= g->n[k];
     }
-    if (cells > (int64_t(1) << 34)) return fail(FV_EINVAL, "grid has too many cells");
+    // cell indices within one sample are 32-bit in the kernels
+    if (cells > INT32_MAX) return fail(FV_EINVAL, "grid has more than 2^31 - 1 cells");
     return FV_OK;
 }
 

@@ -31,6 +31,9 @@ FV_DECLARE_UNIT(unit_scalar3d)
 #define FV_ENTRY_H(D, E, R, F, X, Y, Z, NT, H) \
     RegEntry{D, E, R, F, make_stage_kernel<D, E, R, F, X, Y, Z, NT, H>()}
 
+#define FV_ENTRY_Z(E, R, F, X, Y, Z, NT, WPE) \
+    RegEntry{3, E, R, F, make_stage_kernel_z<E, R, F, X, Y, Z, NT, WPE>()}
+
 #define FV_ALL_RF(D, E, X, Y, Z, NT)                                                          \
     FV_ENTRY(D, E, REC_FIRST, FLUX_RUSANOV, X, Y, Z, NT), FV_ENTRY(D, E, REC_FIRST, FLUX_HLL, X, Y, Z, NT), \
     FV_ENTRY(D, E, REC_MUSCL, FLUX_RUSANOV, X, Y, Z, NT), FV_ENTRY(D, E, REC_MUSCL, FLUX_HLL, X, Y, Z, NT), \

@@ -252,17 +252,62 @@ stage_kernel(const StageArgs args)
     const int64_t sbase = (int64_t)sample * NF * g.cells;
     const double* src = g.src + sbase;
 
-    // 1. ghost fill + load of the haloed tile into LDS
-    for (int e = threadIdx.x; e < PCELLS; e += NT) {
-        const int px = e % PX;
-        const int py = (e / PX) % PY;
-        const int pz = e / (PX * PY);
-        const int32_t gx = wrap_index(x0 + px - G, nx, args.bc[0]);
-        const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - G, ny, args.bc[1]) : 0;
-        const int32_t gz = (DIM >= 3) ? wrap_index(z0 + pz - G, nz, args.bc[2]) : 0;
-        const int64_t gidx = ((int64_t)gz * ny + gy) * nx + gx;
+    // the thread's cells: cell k is tile cell threadIdx.x + k * NT
+    int32_t cell_g[CPT];   // index in the sample
+    bool cell_ok[CPT];     // inside the tile and the grid
 #pragma unroll
-        for (int q = 0; q < NF; ++q) su[q * PCELLS + e] = src[q * g.cells + gidx];
+    for (int k = 0; k < CPT; ++k) {
+        const int c = threadIdx.x + k * NT;
+        const int cx = c % BX;
+        const int cy = (c / BX) % BY;
+        const int cz = c / (BX * BY);
+        const int32_t gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+        cell_ok[k] = c < CELLS && gx < nx && gy < ny && gz < nz;
+        cell_g[k] = (gz * ny + gy) * nx + gx;   // cells < 2^31
+    }
+    const double* un = g.un + sbase;
+    double unr[CPT][NF];
+
+    // 1. ghost fill + load of the haloed tile into LDS: every load of the thread is issued
+    //    before the first LDS store, so the tile costs one memory round trip
+    {
+        constexpr int LPT = (PCELLS + NT - 1) / NT;
+        double v[LPT][NF];
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if ((k + 1) * NT <= PCELLS || e < PCELLS) {
+                const int px = e % PX;
+                const int py = (e / PX) % PY;
+                const int pz = e / (PX * PY);
+                const int32_t gx = wrap_index(x0 + px - G, nx, args.bc[0]);
+                const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - G, ny, args.bc[1]) : 0;
+                const int32_t gz = (DIM >= 3) ? wrap_index(z0 + pz - G, nz, args.bc[2]) : 0;
+                const int32_t gidx = (gz * ny + gy) * nx + gx;   // cells < 2^31
+#pragma unroll
+                for (int q = 0; q < NF; ++q) v[k][q] = src[q * g.cells + gidx];
+            }
+        }
+        // U^n of the thread's cells (stages >= 2), requested with the tile so that its
+        // latency hides behind the faces (not where the fluxes are held in registers: there
+        // the extra registers cost more than the wait)
+        if (!HOLD && args.use_un) {
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) {
+                if (cell_ok[k]) {
+#pragma unroll
+                    for (int q = 0; q < NF; ++q) unr[k][q] = un[q * g.cells + cell_g[k]];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if ((k + 1) * NT <= PCELLS || e < PCELLS) {
+#pragma unroll
+                for (int q = 0; q < NF; ++q) su[q * PCELLS + e] = v[k][q];
+            }
+        }
     }
     __syncthreads();
 
@@ -276,17 +321,14 @@ stage_kernel(const StageArgs args)
     double m = 0.0;
     bool bad = false;
     double* dst = g.dst + sbase;
-    const double* un = g.un + sbase;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
+        if (!cell_ok[k]) continue;
         const int c = threadIdx.x + k * NT;
-        if (c >= CELLS) break;
         const int cx = c % BX;
         const int cy = (c / BX) % BY;
         const int cz = c / (BX * BY);
-        const int32_t gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
-        if (gx >= nx || gy >= ny || gz >= nz) continue;
-        const int64_t gidx = ((int64_t)gz * ny + gy) * nx + gx;
+        const int32_t gidx = cell_g[k];
         const int lc = ((cz + GZ) * PY + (cy + GY)) * PX + (cx + G);
         const int fxm = (cz * BY + cy) * (BX + 1) + cx;
         const int fym = NFX + (cz * (BY + 1) + cy) * BX + cx;
@@ -300,7 +342,7 @@ stage_kernel(const StageArgs args)
             if (DIM >= 3) acc = acc + ((F[fzm + BX * BY] - F[fzm]) * g.ph.inv_dx[2]);
             const double rhs = -acc;
             const double up = HOLD ? src[q * g.cells + gidx] : su[q * PCELLS + lc];
-            const double u0 = args.use_un ? un[q * g.cells + gidx] : up;
+            const double u0 = args.use_un ? (HOLD ? un[q * g.cells + gidx] : unr[k][q]) : up;
             out[q] = u0 + (beta * ((up - u0) + (dt * rhs)));
             dst[q * g.cells + gidx] = out[q];
         }

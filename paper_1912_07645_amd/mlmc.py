@@ -11,6 +11,8 @@ same launches (fv_evolve_multi), each sample with its own time step; the level s
 """
 from __future__ import annotations
 
+import time
+
 import torch
 
 from .solver import Solver, Stats, evolve_multi, mlmc_combine
@@ -30,6 +32,28 @@ class MultilevelRun:
     def group_batch(self, l: int) -> int:
         """Samples on grid l: level l's fine samples, then level l+1's coarse partners."""
         return self.Ms[l] + (self.Ms[l + 1] if l + 1 < len(self.Ms) else 0)
+
+    def tune(self, states, cfl, steps=4, reps=3) -> int:
+        """Pick the tile variant (shared by every grid: one launch covers them all) by timing
+        `steps` multi-grid steps of copies of `states` per variant; returns the variant."""
+        best, best_t = 0, None
+        for v in range(self.solvers[0].num_variants()):
+            for s in self.solvers:
+                s.set_variant(v)
+            ts = []
+            for _ in range(reps + 1):
+                G = [U.clone() for U in states]
+                torch.cuda.synchronize(self.device)
+                t0 = time.perf_counter()
+                self.evolve(G, 1e30, cfl, max_steps=steps)
+                torch.cuda.synchronize(self.device)
+                ts.append(time.perf_counter() - t0)
+            t = min(ts[1:])
+            if best_t is None or t < best_t:
+                best, best_t = v, t
+        for s in self.solvers:
+            s.set_variant(best)
+        return best
 
     def evolve(self, states, t_end, cfl, max_steps=10**9):
         """Evolve every group (list of device tensors, one per grid) from t = 0 to t_end."""

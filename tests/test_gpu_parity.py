@@ -40,7 +40,9 @@ def test_device_division_and_sqrt_are_correctly_rounded():
     r = torch.empty_like(A)
     fv.fv_check_arith(A, Bt, q, r)
     qh, rh = q.cpu().numpy(), r.cpu().numpy()
-    assert np.array_equal(qh, a / b)
+    with np.errstate(over="ignore", under="ignore"):   # quotients past the range are +-inf / 0
+        expect = a / b
+    assert np.array_equal(qh, expect)
     assert np.array_equal(rh, np.sqrt(a))
 
 
@@ -141,6 +143,22 @@ def test_kh3d_small_bitwise():
         G, gt, gs, ge, st = gpu_evolve(p, U0, 10.0, 0.4, max_steps=12, mode="advance", variant=v)
         assert gs[0] == 12 and gt[0] == rt[0]
         assert_parity(G, R, what=f"kh3d variant {v}")
+
+
+def test_3d_hot_variants_ragged_transmissive_batched():
+    """3D WENO3 + HLLC on a ragged 37 x 19 x 45 grid with transmissive boundaries, a batch of
+    six samples: every tile variant (cube tiles and z-marching column blocks, whose x, y
+    and z extents all end inside a tile here) equals the oracle bit for bit."""
+    p = O.Problem(dim=3, n=(37, 19, 45), eq="euler", flux="hllc", recon="weno3",
+                  integrator="ssprk3", bc=("transmissive",) * 3)
+    U0 = np.concatenate([_initial(p, 31 + b) for b in range(3)])
+    note("3d ragged oracle")
+    R, rt, rs, re = O.evolve(p, U0, 1e3, 0.4, max_steps=5)
+    for v in range(solver_for(p).num_variants()):
+        note("3d ragged gpu variant", v)
+        G, gt, gs, ge, st = gpu_evolve(p, U0, 1e3, 0.4, max_steps=5, mode="advance", variant=v)
+        assert np.all(gs == 5) and np.array_equal(gt, rt)
+        assert_parity(G, R, what=f"3d ragged variant {v}")
 
 
 # --------------------------------------------------------------------------- batching
@@ -272,30 +290,33 @@ def test_kh3d_full_size_sampled_cells():
     M, bad = O.max_speed(p, U0[0])
     assert not bad
     dt = 0.4 / M
-    s = solver_for(p)
-    U = torch.from_numpy(U0).to("cuda")
-    t = torch.zeros(1, dtype=torch.float64, device="cuda")
-    k = torch.zeros(1, dtype=torch.int64, device="cuda")
-    note("kh3d 512 gpu step")
-    st = s.advance(U, t, 10.0, 0.4, 1, k)
-    assert st == 0 and int(k[0]) == 1 and float(t[0]) == dt
-    G = U.cpu().numpy()
-    del U
-    torch.cuda.empty_cache()
     rng = np.random.default_rng(3)
-    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, n // 4, 7), (3, 255, 500)]
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, n // 4, 7), (3, 255, 500),
+           (15, 14, 31), (16, 15, 32), (31, 6, 63), (32, 7, 64)]   # tile and segment edges
     pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(20)]
     r = 6
     h = 2 * r + 1
     pb = O.Problem(dim=3, n=(h, h, h), eq="euler", flux="hllc", recon="weno3",
                    integrator="ssprk3", hi=(h / n, h / n, h / n))
+    refs = {}
     for (i, j, kz) in pts:
         idx = [(np.arange(c - r, c + r + 1) % n) for c in (kz, j, i)]
         block = U0[0][:, idx[0]][:, :, idx[1]][:, :, :, idx[2]]
-        out = O.step(pb, block, dt)
-        ref = out[:, r, r, r]
-        got = G[0, :, kz, j, i]
-        assert np.array_equal(got, ref), ((i, j, kz), got, ref)
+        refs[(i, j, kz)] = O.step(pb, block, dt)[:, r, r, r]
+    s = solver_for(p)
+    for v in range(s.num_variants()):
+        s.set_variant(v)
+        U = torch.from_numpy(U0).to("cuda")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        k = torch.zeros(1, dtype=torch.int64, device="cuda")
+        note("kh3d 512 gpu step, variant", v)
+        st = s.advance(U, t, 10.0, 0.4, 1, k)
+        assert st == 0 and int(k[0]) == 1 and float(t[0]) == dt
+        got = {q: U[0, :, q[2], q[1], q[0]].cpu().numpy() for q in pts}
+        del U
+        torch.cuda.empty_cache()
+        for q in pts:
+            assert np.array_equal(got[q], refs[q]), (v, q, got[q], refs[q])
 
 
 def test_tuner_choice_keeps_parity():
@@ -341,21 +362,30 @@ def test_mlmc_pipeline_matches_oracle():
     from paper_1912_07645_amd.mlmc import MultilevelRun
     ns, Ms, T = (16, 32, 64), (24, 8, 4), 0.1
     groups = fi.mlmc_inputs(ns, Ms, seed=1913)
-    note("mlmc gpu")
-    run = MultilevelRun(ns, Ms, dim=2, eq="euler", **MLMC_SCHEME)
-    G = [torch.from_numpy(g).cuda() for g in groups]
-    st, ts, errs = run.evolve(G, T, 0.4)
-    assert st == 0
-    est, levels = run.statistics(G)
     note("mlmc oracle")
     R, rsteps, rlevels, rest = _mlmc_oracle(ns, Ms, groups, T, 0.4, MLMC_SCHEME)
-    for l in range(3):
-        assert_parity(G[l].cpu().numpy(), R[l], what=f"mlmc group {l}")
-        out = levels[l].read()
-        assert out["count"] == Ms[l]
-        assert_parity(out["mean"].cpu().numpy(), rlevels[l].mean, what=f"level {l} mean")
-        assert_parity(out["var"].cpu().numpy(), rlevels[l].variance(), what=f"level {l} var")
-    assert_parity(est.cpu().numpy(), rest, what="mlmc estimate")
+    run = MultilevelRun(ns, Ms, dim=2, eq="euler", **MLMC_SCHEME)
+    for v in range(run.solvers[0].num_variants()):
+        note("mlmc gpu, variant", v)
+        for s in run.solvers:
+            s.set_variant(v)
+        G = [torch.from_numpy(g).cuda() for g in groups]
+        st, ts, errs = run.evolve(G, T, 0.4)
+        assert st == 0
+        est, levels = run.statistics(G)
+        for l in range(3):
+            assert_parity(G[l].cpu().numpy(), R[l], what=f"mlmc group {l}, variant {v}")
+            out = levels[l].read()
+            assert out["count"] == Ms[l]
+            assert_parity(out["mean"].cpu().numpy(), rlevels[l].mean, what=f"level {l} mean")
+            assert_parity(out["var"].cpu().numpy(), rlevels[l].variance(), what=f"level {l} var")
+        assert_parity(est.cpu().numpy(), rest, what="mlmc estimate")
+    G = [torch.from_numpy(g).cuda() for g in groups]
+    v = run.tune(G, 0.4, steps=2, reps=1)
+    assert 0 <= v < run.solvers[0].num_variants()
+    assert all(s.tile()[1] == v for s in run.solvers)
+    for l in range(3):   # tuning works on copies
+        assert np.array_equal(G[l].cpu().numpy(), groups[l])
 
 
 def test_multi_group_launch_equals_separate_launches():
@@ -386,7 +416,9 @@ def test_mlmc_full_configuration_sampled():
     run = MultilevelRun(ns, Ms, dim=2, eq="euler", **MLMC_SCHEME)
     G = [torch.from_numpy(g).cuda() for g in groups]
     mass0 = [g[:, 0].sum(axis=(1, 2, 3)) for g in groups]
-    note("mlmc full gpu")
+    note("mlmc full tune")
+    run.tune(G, 0.4)   # the variant the benchmark runs
+    note("mlmc full gpu, variant", run.solvers[0].tile()[1])
     st, ts, errs = run.evolve(G, T, 0.4)
     assert st == 0 and all(bool((t == T).all()) for t in ts)
     est, levels = run.statistics(G)
