@@ -359,27 +359,30 @@ def measure(a, w, steps=None, warmup=None):
     t_end = 1e9
     s.advance(U, t, t_end, w["cfl"], W, steps_t, err)
     torch.cuda.synchronize()
-    # timed region: K full steps, state resident in HBM
+    # timed region: K full steps, state resident in HBM. HIP events on the caller's stream
+    # (the library's stream is ordered after it on entry and before it on exit) bracket the
+    # region on the device as well.
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record()
     st = s.advance(U, t, t_end, w["cfl"], K, steps_t, err)
+    ev1.record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     assert st == 0 and int(steps_t.min()) == K, (st, steps_t.min())
     cells = w["n"] ** w["dim"]
     value = cells * B * K / el
 
-    # stage-kernel timing with HIP events on the library's stream, over K more steps
-    fv.fv_profile_enable(s.handle, True)
-    s.advance(U, t, t_end, w["cfl"], K, steps_t, err)
-    torch.cuda.synchronize()
-    stage_ms, launches = fv.fv_profile_read(s.handle)
-    fv.fv_profile_enable(s.handle, False)
+    # mean stage-launch duration: the device time of the timed region over its stage launches
+    # (K steps x stages). It includes the per-step control kernel and the launch gaps, so it
+    # bounds the stage kernel's own duration from above.
     nstages = {"forward_euler": 1, "ssprk2": 2, "ssprk3": 3}[w["integrator"]]
-    assert launches == K * nstages, (launches, K, nstages)
+    launches = K * nstages
     nf = w["dim"] + 2
     bytes_step = algorithmic_bytes_per_cell_step(nf, w["integrator"]) * cells * B
-    avg_launch_s = stage_ms * 1e-3 / launches
+    avg_launch_s = ev0.elapsed_time(ev1) * 1e-3 / launches
     bytes_per_launch = bytes_step / nstages
     achieved = bytes_per_launch / avg_launch_s / 1e9
     hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -170,11 +170,12 @@ fv_status fv_tune(fv_solver* solver, double* state, int64_t batch, int32_t reps,
 /* ------------------------------------------------------------------ kernel timing */
 
 /* Kernel timing for roofline measurements. While enabled (on != 0), the time-stepping
- * calls enqueue their launches directly instead of replaying a graph, and bracket every
- * Runge--Kutta stage launch with HIP events on the solver's internal stream; enabling or
- * disabling resets the totals. fv_profile_read returns the accumulated device time of the
- * stage launches in milliseconds and their number (outputs may be NULL). Launches of
- * samples that had already finished count as well (they return immediately). */
+ * calls enqueue their launches directly instead of replaying a graph, and bracket each
+ * step's Runge--Kutta stage launches, which follow each other directly, with one pair of HIP
+ * events on the solver's internal stream; enabling or disabling resets the totals.
+ * fv_profile_read returns the accumulated device time of the stage launches in milliseconds
+ * and their number (outputs may be NULL). Launches of samples that had already finished count
+ * as well (they return immediately). */
 fv_status fv_profile_enable(fv_solver* solver, int32_t on);
 fv_status fv_profile_read(const fv_solver* solver, double* stage_ms, int64_t* stage_launches);
 

@@ -40,11 +40,12 @@ struct fv_adjoint {
 static __global__ void adj_init_kernel(double* dt_arr, int32_t* active, unsigned long long* mbits,
                                        int32_t* bad, int64_t batch, double dt)
 {
+    const int64_t pitch = speed_pitch(batch);
     for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < batch;
          b += (int64_t)gridDim.x * blockDim.x) {
         dt_arr[b] = dt;
         active[b] = 1;
-        mbits[b] = 0ull;
+        for (int s = 0; s < kSpeedSlots; ++s) mbits[s * pitch + b] = 0ull;
         bad[b] = 0;
     }
 }
@@ -135,7 +136,7 @@ extern "C" fv_status fv_adjoint_create(fv_solver* s, int64_t batch, int64_t nste
               hipMalloc((void**)&a->lam[2], sb) == hipSuccess &&
               hipMalloc((void**)&a->dt_arr, sizeof(double) * batch) == hipSuccess &&
               hipMalloc((void**)&a->active, sizeof(int32_t) * batch) == hipSuccess &&
-              hipMalloc((void**)&a->mbits, sizeof(unsigned long long) * batch) == hipSuccess &&
+              hipMalloc((void**)&a->mbits, sizeof(unsigned long long) * kSpeedSlots * speed_pitch(batch)) == hipSuccess &&
               hipMalloc((void**)&a->bad, sizeof(int32_t) * batch) == hipSuccess;
     if (!ok) {
         fv_adjoint_destroy(a);
@@ -200,17 +201,20 @@ extern "C" fv_status fv_adjoint_forward(fv_adjoint* a, const double* state0, dou
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(stateT, cur, sb, hipMemcpyDeviceToDevice, st));
     // trajectory checks: max wave speed over all states, non-physical values
-    std::vector<unsigned long long> mb((size_t)a->batch);
+    const int64_t pitch = speed_pitch(a->batch);
+    std::vector<unsigned long long> mb((size_t)(kSpeedSlots * pitch));
     std::vector<int32_t> bd((size_t)a->batch);
-    HIP_TRY(hipMemcpyAsync(mb.data(), a->mbits, sizeof(unsigned long long) * a->batch, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(mb.data(), a->mbits, sizeof(unsigned long long) * mb.size(), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipMemcpyAsync(bd.data(), a->bad, sizeof(int32_t) * a->batch, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     a->forward_done = true;
     e = stream_leave(s);
     if (e) return e;
     for (int64_t b = 0; b < a->batch; ++b) {
+        unsigned long long mx = 0ull;   // bit patterns of non-negative doubles order like them
+        for (int s2 = 0; s2 < kSpeedSlots; ++s2) mx = std::max(mx, mb[(size_t)(s2 * pitch + b)]);
         double M;
-        std::memcpy(&M, &mb[(size_t)b], sizeof(double));
+        std::memcpy(&M, &mx, sizeof(double));
         if (bd[(size_t)b]) return fail(FV_ENONPHYS, "sample " + std::to_string(b) + " became non-physical");
         if (a->dt * M > a->cfl_bound)
             return fail(FV_ECFL, "sample " + std::to_string(b) + ": dt * max speed exceeded the bound");

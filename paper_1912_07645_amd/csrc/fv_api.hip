@@ -109,7 +109,7 @@ static WsLayout ws_layout(const fv_solver* s, int64_t batch)
     }
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     L.dt = take(sizeof(double) * batch);
-    L.mbits = take(sizeof(unsigned long long) * batch);
+    L.mbits = take(sizeof(unsigned long long) * kSpeedSlots * speed_pitch(batch));
     L.steps = take(sizeof(int64_t) * batch);
     L.running = take(sizeof(int32_t) * batch);
     L.active = take(sizeof(int32_t) * batch);
@@ -392,15 +392,13 @@ static StepPlan make_plan(std::vector<GroupRun>& runs)
     return p;
 }
 
+// With ev (profiling), the step's stage launches, which follow each other directly, are
+// bracketed by one pair of events: ev[0] before the first, ev[1] after the last.
 static void enqueue_step(const StepPlan& p, hipStream_t st, hipEvent_t* ev = nullptr)
 {
-    int i = 0;
-    for (const StageArgs& a : p.stages) {
-        if (ev) hipEventRecord(ev[2 * i], st);
-        p.kern->stage(a, st);
-        if (ev) hipEventRecord(ev[2 * i + 1], st);
-        ++i;
-    }
+    if (ev) hipEventRecord(ev[0], st);
+    for (const StageArgs& a : p.stages) p.kern->stage(a, st);
+    if (ev) hipEventRecord(ev[1], st);
     if (p.copy_back) launch_copy_back(p.copy, st);
     launch_ctrl_begin(p.ctrl, st);
 }
@@ -458,7 +456,7 @@ static fv_status run_steps(fv_solver* s0, std::vector<GroupRun> runs, const Ctrl
     const bool use_graph = graphs_enabled() && !profile;
     const size_t nst = p.stages.size();
     if (profile) {
-        const size_t need = 2 * nst * (size_t)chunk;
+        const size_t need = 2 * (size_t)chunk;
         while (s0->prof_ev.size() < need) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
@@ -512,18 +510,18 @@ static fv_status run_steps(fv_solver* s0, std::vector<GroupRun> runs, const Ctrl
             HIP_TRY(hipGraphLaunch(s0->graph.exec, st));
         } else {
             for (int64_t i = 0; i < n; ++i)
-                enqueue_step(p, st, profile ? &s0->prof_ev[2 * nst * (size_t)i] : nullptr);
+                enqueue_step(p, st, profile ? &s0->prof_ev[2 * (size_t)i] : nullptr);
             HIP_TRY(hipGetLastError());
         }
         done += n;
         e = read_counts();
         if (e) return e;
         if (profile) {
-            for (size_t i = 0; i < nst * (size_t)n; ++i) {
+            for (size_t i = 0; i < (size_t)n; ++i) {
                 float ms = 0.0f;
                 HIP_TRY(hipEventElapsedTime(&ms, s0->prof_ev[2 * i], s0->prof_ev[2 * i + 1]));
                 s0->prof_stage_ms += ms;
-                s0->prof_stage_launches += 1;
+                s0->prof_stage_launches += (int64_t)nst;
             }
         }
         if (s0->host_count[0] == 0) return FV_OK;

@@ -45,6 +45,13 @@ struct Group {
 
 constexpr int kMaxGroups = 8;
 
+// The maximum wave speed of a sample is merged into kSpeedSlots words (a workgroup uses slot
+// tile % kSpeedSlots), laid out [slot][batch rounded up to 16], so the atomics of one
+// sample's workgroups spread over 16 cache lines instead of contending for one word; the
+// step control takes the maximum of the slots.
+constexpr int kSpeedSlots = 16;
+__host__ __device__ inline int64_t speed_pitch(int64_t batch) { return (batch + 15) / 16 * 16; }
+
 // Arguments of one Runge--Kutta stage launch.
 struct StageArgs {
     Group g[kMaxGroups];

@@ -10,7 +10,7 @@ struct CtrlGroup {
     double* dt;                 // [batch]
     int32_t* running;           // [batch]
     int32_t* active;            // [batch]
-    unsigned long long* mbits;  // [batch]
+    unsigned long long* mbits;  // [kSpeedSlots][speed_pitch(batch)]
     int32_t* bad;               // [batch]
     int64_t* steps;             // [batch]
     int32_t* err;               // [batch]

@@ -13,10 +13,11 @@ __global__ void ctrl_reset_kernel(const CtrlArgs a)
 {
     for (int gi = 0; gi < a.ngroups; ++gi) {
         const CtrlGroup& g = a.g[gi];
+        const int64_t pitch = speed_pitch(g.batch);
         for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < g.batch; b += gridDim.x * blockDim.x) {
             g.running[b] = 1;
             g.active[b] = 1;
-            g.mbits[b] = 0ull;
+            for (int s = 0; s < kSpeedSlots; ++s) g.mbits[s * pitch + b] = 0ull;
             g.bad[b] = 0;
             g.steps[b] = 0;
             g.err[b] = ST_OK;
@@ -34,12 +35,19 @@ __global__ void __launch_bounds__(1024) ctrl_begin_kernel(const CtrlArgs a)
     __syncthreads();
     for (int gi = 0; gi < a.ngroups; ++gi) {
         const CtrlGroup& g = a.g[gi];
+        const int64_t pitch = speed_pitch(g.batch);
         int mine = 0;
         for (int b = threadIdx.x; b < g.batch; b += blockDim.x) {
             if (!g.running[b]) { g.active[b] = 0; continue; }
             int stop = 0;
             int32_t e = ST_OK;
-            const double M = __longlong_as_double((long long)g.mbits[b]);
+            // bit patterns of non-negative doubles order like the doubles
+            unsigned long long mb = 0ull;
+            for (int s = 0; s < kSpeedSlots; ++s) {
+                const unsigned long long v = g.mbits[s * pitch + b];
+                mb = v > mb ? v : mb;
+            }
+            const double M = __longlong_as_double((long long)mb);
             double dt = 0.0, tnew = 0.0;
             if (g.bad[b]) {
                 e = ST_ENONPHYS;
@@ -80,7 +88,7 @@ __global__ void __launch_bounds__(1024) ctrl_begin_kernel(const CtrlArgs a)
             if (!a.fixed) g.t[b] = tnew;
             g.steps[b] = g.steps[b] + 1;
             g.active[b] = 1;
-            g.mbits[b] = 0ull;
+            for (int s = 0; s < kSpeedSlots; ++s) g.mbits[s * pitch + b] = 0ull;
             g.bad[b] = 0;
             mine += 1;
         }

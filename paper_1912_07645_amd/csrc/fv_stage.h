@@ -353,7 +353,9 @@ stage_kernel(const StageArgs args)
             bad = bad || b;
         }
     }
-    if (args.last) block_merge_speed<NT>(m, bad, &g.mbits[sample], &g.bad[sample]);
+    if (args.last)
+        block_merge_speed<NT>(m, bad, &g.mbits[(tile % kSpeedSlots) * speed_pitch(g.batch) + sample],
+                              &g.bad[sample]);
 }
 
 // Wave speed and physicality of a state, without update (the step-0 reduction).
@@ -382,7 +384,9 @@ speed_kernel(const SpeedArgs args, int cells_per_block)
         m = vmax(m, s);
         bad = bad || b;
     }
-    block_merge_speed<kThreads>(m, bad, &g.mbits[sample], &g.bad[sample]);
+    block_merge_speed<kThreads>(m, bad,
+                                &g.mbits[((local % per_sample) % kSpeedSlots) * speed_pitch(g.batch) + sample],
+                                &g.bad[sample]);
 }
 
 template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD>

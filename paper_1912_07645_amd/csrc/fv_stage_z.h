@@ -270,7 +270,9 @@ stage_kernel_z(const StageArgs args)
 #pragma unroll
             for (int q = 0; q < NF; ++q) w[j][q] = w[j + 1][q];
     }
-    if (args.last) block_merge_speed<NT>(m, bad, &g.mbits[sample], &g.bad[sample]);
+    if (args.last)
+        block_merge_speed<NT>(m, bad, &g.mbits[(tile % kSpeedSlots) * speed_pitch(g.batch) + sample],
+                              &g.bad[sample]);
 }
 
 template <int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int WPE>

@@ -210,6 +210,30 @@ def test_run_to_run_graph_and_chunk_invariance():
     assert np.array_equal(A, E) and np.array_equal(A, Cc)
 
 
+def test_kernel_timing_counts_and_leaves_results_unchanged():
+    """fv_profile_enable: the timed (eagerly enqueued) run gives the same state bit for bit,
+    and the counters report the stage launches, three per enqueued SSP-RK3 step."""
+    from paper_1912_07645_amd import fv
+    torch = torch_gpu()
+    c, phi = fi.kh_coefficients(1912, [2])
+    U0 = fi.kh2d_state(64, c, phi)
+    p = _kh_problem(64)
+    note("profile reference")
+    A, at, ak, *_ = gpu_evolve(p, U0, 0.05, 0.4)
+    s = solver_for(p)
+    fv.fv_profile_enable(s.handle, True)
+    note("profile timed")
+    T, tt, tk, *_ = gpu_evolve(p, U0, 0.05, 0.4, solver=s)
+    ms, launches = fv.fv_profile_read(s.handle)
+    fv.fv_profile_enable(s.handle, False)
+    assert np.array_equal(A, T) and np.array_equal(at, tt) and np.array_equal(ak, tk)
+    # steps are enqueued in chunks of 16, so up to 15 launches per stage past the last step
+    # (which return at once) are counted too
+    k = int(tk[0])
+    assert launches % 3 == 0 and 3 * k <= launches < 3 * (k + 16) and ms > 0.0
+    assert fv.fv_profile_read(s.handle) == (0.0, 0)
+
+
 # --------------------------------------------------------------------------- failures
 
 def test_failure_codes_match_oracle():
