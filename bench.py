@@ -30,18 +30,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, 8 TB/s
-# FP64 vector peak without FMA: 256 CUs x 64 FP64 lanes per clock x 2.4 GHz = 39.3e12 ops/s
-# (the published 78.6 TFLOP/s counts an FMA as 2 flops; the arithmetic contract forbids FMA
-# contraction, so every operation is one lane-op)
+# FP64 issue peak: 256 CUs x 64 FP64 lanes per clock x 2.4 GHz = 39.3e12 lane-ops/s. The
+# published 78.6 TFLOP/s counts an FMA as 2 flops; here every FP64 operation, an FMA
+# included, is one lane-op, since the stage kernel is bound by issuing them.
 FP64_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 
 # FP64 lane-operations the arithmetic contract needs, with each face counted once: every
-# + - x and comparison/select counts 1, a correctly rounded division 10 and a square root 14
-# (the lengths of their gfx950 expansions). Derivation in the design notes.
-WENO3_PER_COMPONENT = 50        # both face values of one component (shared indicator)
+# + - x, fused multiply-add and comparison/select counts 1, a correctly rounded division 10
+# and a square root 14 (the lengths of their gfx950 expansions). Derivation in the design
+# notes.
+WENO3_PER_COMPONENT = 43        # both face values of one component (shared indicator)
 EULER_PRIM = {1: 31, 2: 34, 3: 37}            # primitives of one face state
 EULER_FLUX = {1: 4, 2: 5, 3: 6}                # physical flux of one face state
-HLLC = {1: 81, 2: 91, 3: 101}                  # wave speeds, contact, star state, selects
+HLLC = {1: 76, 2: 85, 3: 94}                   # wave speeds, contact, star state, selects
 DIVERGENCE_RK = {1: 3 + 5, 2: 6 + 5, 3: 9 + 5}  # per component: flux difference sum, stage
 CFL_CELL = {1: 45, 2: 47, 3: 55}              # per cell, last stage only
 

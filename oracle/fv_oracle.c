@@ -22,8 +22,11 @@
  * ghost fill into a padded copy, reconstruction of the two face values of every cell,
  * numerical flux at every face, flux-difference divergence, Runge--Kutta combination.
  * Nothing is blocked, fused or reordered. Each floating-point expression is written with
- * explicit parentheses in the evaluation order of the arithmetic contract (no FMA, no
- * reassociation; compile with -ffp-contract=off and without fast-math).
+ * explicit parentheses in the evaluation order of the arithmetic contract (no
+ * reassociation; compile with -ffp-contract=off and without fast-math). Fused
+ * multiply-adds (one rounding) appear only where written as fma(): in the WENO3 smoothness
+ * terms, candidate and numerator, and in the HLLC contact-speed numerator, star energy and
+ * star flux.
  *
  * Readings where the paper is silent (it names the schemes but prints no formulas):
  *   - reconstruction acts component-wise on the conserved variables;
@@ -192,7 +195,7 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
         /* HLLC: contact speed S* and the star state on the side it selects. */
         double DL = UL[0] * (SL - uL);
         double DR = UR[0] * (SR - uR);
-        double num = (wr.p - wl.p) + ((UL[1 + nd] * (SL - uL)) - (UR[1 + nd] * (SR - uR)));
+        double num = (wr.p - wl.p) + fma(UL[1 + nd], SL - uL, -(UR[1 + nd] * (SR - uR)));
         double den = DL - DR;
         double Ss = num / den;
         const double* UK; const double* FK; const oc_prim* wK; double SK, DK;
@@ -204,9 +207,9 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
         Us[0] = f;
         for (int k = 0; k < dim; ++k)
             Us[1 + k] = (k == nd) ? (f * Ss) : (f * wK->u[k]);
-        Us[dim + 1] = f * ((UK[dim + 1] * wK->ir) + ((Ss - uK) * (Ss + (wK->p / DK))));
+        Us[dim + 1] = f * fma(UK[dim + 1], wK->ir, (Ss - uK) * (Ss + (wK->p / DK)));
         for (int q = 0; q < nf; ++q)
-            Fh[q] = FK[q] + (SK * (Us[q] - UK[q]));
+            Fh[q] = fma(SK, Us[q] - UK[q], FK[q]);
         return;
     }
     /* scalar equations */
@@ -253,13 +256,13 @@ double oc_weno3(double a, double b, double c)
     const double eps = 1e-6;
     double d0 = b - a;
     double d1 = c - b;
-    double t0 = eps + (d1 * d1);
+    double t0 = fma(d1, d1, eps);
     t0 = t0 * t0;
-    double t1 = eps + (d0 * d0);
+    double t1 = fma(d0, d0, eps);
     t1 = t1 * t1;
     double q0 = 0.5 * (b + c);
-    double q1 = (1.5 * b) - (0.5 * a);
-    return (((2.0 * t1) * q0) + (t0 * q1)) / ((2.0 * t1) + t0);
+    double q1 = fma(1.5, b, -(0.5 * a));
+    return fma(2.0 * t1, q0, t0 * q1) / ((2.0 * t1) + t0);
 }
 
 /* Face values of the cell with stencil values (um, u0, up) = (U_{i-1}, U_i, U_{i+1}):

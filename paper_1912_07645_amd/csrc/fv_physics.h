@@ -109,7 +109,7 @@ __device__ __forceinline__ void euler_numflux(const double* UL, const double* UR
     const double mL = pick<DIM>(UL + 1, nd), mR = pick<DIM>(UR + 1, nd);
     const double DL = UL[0] * (SL - uL);
     const double DR = UR[0] * (SR - uR);
-    const double num = (wr.p - wl.p) + ((mL * (SL - uL)) - (mR * (SR - uR)));
+    const double num = (wr.p - wl.p) + __builtin_fma(mL, SL - uL, -(mR * (SR - uR)));
     const double den = DL - DR;
     const double Ss = num / den;
     const bool left = (Ss >= 0.0);
@@ -131,10 +131,10 @@ __device__ __forceinline__ void euler_numflux(const double* UL, const double* UR
         const double vk = left ? wl.u[k] : wr.u[k];
         Us[1 + k] = (k == nd) ? (f * Ss) : (f * vk);
     }
-    Us[DIM + 1] = f * ((UK[DIM + 1] * irK) + ((Ss - uK) * (Ss + (pK / DK))));
+    Us[DIM + 1] = f * __builtin_fma(UK[DIM + 1], irK, (Ss - uK) * (Ss + (pK / DK)));
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
-        const double star = FK[q] + (SK * (Us[q] - UK[q]));
+        const double star = __builtin_fma(SK, Us[q] - UK[q], FK[q]);
         Fh[q] = takeL ? FL[q] : (takeR ? FR[q] : star);
     }
 }
@@ -184,18 +184,19 @@ __device__ __forceinline__ double minmod(double a, double b)
 
 // Third-order WENO (Jiang--Shu indicators, eps = 1e-6, power 2): the value at the face
 // between b and c from cells (a, b, c), candidates (b+c)/2 and (3b-a)/2 with linear weights
-// 2/3 and 1/3, combined with a single division.
+// 2/3 and 1/3, combined with a single division. The smoothness terms, the candidate (3b-a)/2
+// and the numerator are fused multiply-adds (one rounding each).
 __device__ __forceinline__ double weno3(double a, double b, double c)
 {
     const double d0 = b - a;
     const double d1 = c - b;
-    double t0 = 1e-6 + (d1 * d1);
+    double t0 = __builtin_fma(d1, d1, 1e-6);
     t0 = t0 * t0;
-    double t1 = 1e-6 + (d0 * d0);
+    double t1 = __builtin_fma(d0, d0, 1e-6);
     t1 = t1 * t1;
     const double q0 = 0.5 * (b + c);
-    const double q1 = (1.5 * b) - (0.5 * a);
-    return (((2.0 * t1) * q0) + (t0 * q1)) / ((2.0 * t1) + t0);
+    const double q1 = __builtin_fma(1.5, b, -(0.5 * a));
+    return __builtin_fma(2.0 * t1, q0, t0 * q1) / ((2.0 * t1) + t0);
 }
 
 // Left and right states at the face between cells i-1 and i from the stencil
@@ -215,19 +216,19 @@ __device__ __forceinline__ void reconstruct(double a, double b, double c, double
         // candidate (b + c)/2: (b - c)^2 equals (c - b)^2 and b + c equals c + b bit for bit,
         // so each is computed once.
         const double dbc = c - b;
-        double tbc = 1e-6 + (dbc * dbc);
+        double tbc = __builtin_fma(dbc, dbc, 1e-6);
         tbc = tbc * tbc;
         const double q0 = 0.5 * (b + c);
         const double dab = b - a;
-        double tab = 1e-6 + (dab * dab);
+        double tab = __builtin_fma(dab, dab, 1e-6);
         tab = tab * tab;
-        const double q1L = (1.5 * b) - (0.5 * a);
-        uL = (((2.0 * tab) * q0) + (tbc * q1L)) / ((2.0 * tab) + tbc);
+        const double q1L = __builtin_fma(1.5, b, -(0.5 * a));
+        uL = __builtin_fma(2.0 * tab, q0, tbc * q1L) / ((2.0 * tab) + tbc);
         const double ddc = c - d;
-        double tdc = 1e-6 + (ddc * ddc);
+        double tdc = __builtin_fma(ddc, ddc, 1e-6);
         tdc = tdc * tdc;
-        const double q1R = (1.5 * c) - (0.5 * d);
-        uR = (((2.0 * tdc) * q0) + (tbc * q1R)) / ((2.0 * tdc) + tbc);
+        const double q1R = __builtin_fma(1.5, c, -(0.5 * d));
+        uR = __builtin_fma(2.0 * tdc, q0, tbc * q1R) / ((2.0 * tdc) + tbc);
     }
 }
 
