@@ -145,6 +145,22 @@ def test_kh3d_small_bitwise():
         assert_parity(G, R, what=f"kh3d variant {v}")
 
 
+def test_2d_hot_variants_ragged_transmissive_batched():
+    """2D WENO3 + HLLC on a ragged 70 x 83 grid with transmissive boundaries, a batch of four
+    samples: every tile variant (tiles, and y-marching strips whose last band and segment end
+    inside the grid) equals the oracle bit for bit."""
+    p = O.Problem(dim=2, n=(70, 83), eq="euler", flux="hllc", recon="weno3",
+                  integrator="ssprk3", bc=("transmissive",) * 3)
+    U0 = np.concatenate([_initial(p, 41 + b) for b in range(2)])
+    note("2d ragged oracle")
+    R, rt, rs, re = O.evolve(p, U0, 1e3, 0.4, max_steps=5)
+    for v in range(solver_for(p).num_variants()):
+        note("2d ragged gpu variant", v)
+        G, gt, gs, ge, st = gpu_evolve(p, U0, 1e3, 0.4, max_steps=5, mode="advance", variant=v)
+        assert np.all(gs == 5) and np.array_equal(gt, rt)
+        assert_parity(G, R, what=f"2d ragged variant {v}")
+
+
 def test_3d_hot_variants_ragged_transmissive_batched():
     """3D WENO3 + HLLC on a ragged 37 x 19 x 45 grid with transmissive boundaries, a batch of
     six samples: every tile variant (cube tiles and z-marching column blocks, whose x, y
