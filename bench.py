@@ -239,6 +239,8 @@ def run_adjoint(a, w):
     j0, j1 = band_rows(n)
     K = a.steps if a.steps is not None else w["steps"]
     W = a.warmup if a.warmup is not None else w["warmup"]
+    tuned = s.tune(U0d) if a.variant is None else a.variant   # the forward stage's tile
+    s.set_variant(tuned)
     adj = Adjoint(s, B, N, dt, cfl_bound=0.6)
     fwd, grad = [], []
     for r in range(W + K):
@@ -264,7 +266,8 @@ def run_adjoint(a, w):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w["name"], "grid": [n, n], "samples": B, "time_steps": N,
                    "dt": dt, "checkpoint_every": adj.every, "outer_state_speed_check": outer,
-                   "step": "one gradient evaluation (forward with checkpoints + reverse sweep)"},
+                   "step": "one gradient evaluation (forward with checkpoints + reverse sweep)",
+                   "forward_tile": list(s.tile()[0]), "tuned_variant": tuned},
         "forward_ms": tf * 1e3, "gradient_ms": tg * 1e3, "adjoint_over_forward_cost": tg / tf,
         "roofline": None,
     }

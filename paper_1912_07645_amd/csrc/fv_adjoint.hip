@@ -7,8 +7,9 @@
 // sum_i lam_i . L_i = sum_faces F_f . w_f, w_f = (lam_right - lam_left) / dx. Every face
 // therefore contributes (dF_f / dU_c)^T w_f to the four cells c of its stencil, through
 // g_L = (dF/dU_L)^T w and g_R = (dF/dU_R)^T w and the reconstruction's partial derivatives.
-// The faces of a tile store (g_L, g_R, minmod branch codes) in LDS; each cell then adds its
-// four faces per axis in a fixed order, with no atomics, so results are reproducible.
+// The faces of a tile store (g_L, g_R, minmod branch codes) in LDS, one axis at a time; each
+// cell then adds that axis's four faces in a fixed order, with no atomics, so results are
+// reproducible.
 // Branches follow the forward pass: the larger Rusanov speed (ties to the right state), the
 // minmod argument selected (ties as the forward comparison), sign(0) = 0 for |u|.
 #include "fv_adjoint.h"
@@ -104,10 +105,12 @@ adjoint_stage_kernel(const AdjArgs a)
     constexpr int UX = T::UX, UY = T::UY, LX = T::LX, LY = T::LY;
     constexpr int NFX = T::NFX, NFACES = T::NFACES, EXN = T::EXN, EYN = T::EYN;
     constexpr int UC = UX * UY, LC = LX * LY;
+    constexpr int NFY = T::NFY;
+    constexpr int MAXF = NFX > NFY ? NFX : NFY;   // faces of one axis
     __shared__ double su[NF * UC];
     __shared__ double sl[NF * LC];
-    __shared__ double sg[2 * NF * NFACES];   // g_L, g_R per face
-    __shared__ int scode[NFACES];            // minmod codes, 2 bits per component and side
+    __shared__ double sg[2 * NF * MAXF];   // g_L, g_R per face of the axis in hand
+    __shared__ int scode[MAXF];            // minmod codes, 2 bits per component and side
 
     const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
     const int32_t sample = (int32_t)(blk / a.ntiles);
@@ -120,89 +123,172 @@ adjoint_stage_kernel(const AdjArgs a)
     const double* U = a.U + sbase;
     const double* lam = a.lam + sbase;
 
-    for (int e = threadIdx.x; e < UC; e += NT) {
-        const int px = e % UX, py = e / UX;
-        const int32_t gx = wrap_index(x0 + px - HU, nx, a.bc[0]);
-        const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - HU, ny, a.bc[1]) : 0;
-        const int64_t gi = (int64_t)gy * nx + gx;
+    // the haloed tiles of U and lambda into LDS, every load issued before the first store
+    {
+        constexpr int UPT = (UC + NT - 1) / NT, LPT = (LC + NT - 1) / NT;
+        double vu[UPT][NF], vl[LPT][NF];
 #pragma unroll
-        for (int q = 0; q < NF; ++q) su[q * UC + e] = U[q * a.cells + gi];
-    }
-    for (int e = threadIdx.x; e < LC; e += NT) {
-        const int px = e % LX, py = e / LX;
-        const int32_t gx = wrap_index(x0 + px - HL, nx, a.bc[0]);
-        const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - HL, ny, a.bc[1]) : 0;
-        const int64_t gi = (int64_t)gy * nx + gx;
+        for (int k = 0; k < UPT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if ((k + 1) * NT <= UC || e < UC) {
+                const int px = e % UX, py = e / UX;
+                const int32_t gx = wrap_index(x0 + px - HU, nx, a.bc[0]);
+                const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - HU, ny, a.bc[1]) : 0;
+                const int32_t gi = gy * nx + gx;   // cells < 2^31
 #pragma unroll
-        for (int q = 0; q < NF; ++q) sl[q * LC + e] = lam[q * a.cells + gi];
-    }
-    __syncthreads();
-
-    // faces: (g_L, g_R, codes)
-    for (int f = threadIdx.x; f < NFACES; f += NT) {
-        int nd, fx, fy;   // face between (right cell) and (right cell - e_nd), tile-local
-        if (f < NFX) {
-            nd = 0;
-            fx = f % EXN - R;          // right-cell x offset from x0, in [-R, BX + R]
-            fy = f / EXN;
-        } else {
-            const int l = f - NFX;
-            nd = 1;
-            fx = l % BX;
-            fy = l / BX - R;
-        }
-        const int cu = ((DIM >= 2 ? fy + HU : 0)) * UX + (fx + HU);
-        const int su_stride = (nd == 0) ? 1 : UX;
-        const int cl = ((DIM >= 2 ? fy + HL : 0)) * LX + (fx + HL);
-        const int sl_stride = (nd == 0) ? 1 : LX;
-        double UL[NF], UR[NF], w[NF];
-        int codes = 0;
-        const double inv = (nd == 0) ? a.ph.inv_dx[0] : a.ph.inv_dx[1];
-#pragma unroll
-        for (int q = 0; q < NF; ++q) {
-            const double* s = su + q * UC + cu;
-            const double ua = s[-su_stride], ub = s[0];
-            if (RECON == REC_MUSCL) {
-                const double uam = s[-2 * su_stride], ubp = s[su_stride];
-                const int cL = minmod_code(ua - uam, ub - ua);
-                const int cR = minmod_code(ub - ua, ubp - ub);
-                codes |= (cL | (cR << 2)) << (4 * q);
-                UL[q] = ua + (0.5 * minmod(ua - uam, ub - ua));
-                UR[q] = ub - (0.5 * minmod(ub - ua, ubp - ub));
-            } else {
-                UL[q] = ua;
-                UR[q] = ub;
+                for (int q = 0; q < NF; ++q) vu[k][q] = U[q * a.cells + gi];
             }
-            const double* l = sl + q * LC + cl;
-            w[q] = inv * (l[0] - l[-sl_stride]);
         }
-        const EulerPrim<DIM> pl = euler_prim<DIM>(UL, a.ph);
-        const EulerPrim<DIM> pr = euler_prim<DIM>(UR, a.ph);
-        const double sL = fabs(pick<DIM>(pl.u, nd)) + pl.c;
-        const double sR = fabs(pick<DIM>(pr.u, nd)) + pr.c;
-        const bool selL = sL > sR;
-        const double s = selL ? sL : sR;
-        double jl[NF], jr[NF], gs[NF];
-        euler_flux_jt<DIM>(UL, pl, nd, w, a.ph, jl);
-        euler_flux_jt<DIM>(UR, pr, nd, w, a.ph, jr);
-        if (selL) speed_grad<DIM>(UL, pl, nd, a.ph, gs);
-        else speed_grad<DIM>(UR, pr, nd, a.ph, gs);
-        double wd = 0.0;
 #pragma unroll
-        for (int q = 0; q < NF; ++q) wd = wd + w[q] * (UR[q] - UL[q]);
+        for (int k = 0; k < LPT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if ((k + 1) * NT <= LC || e < LC) {
+                const int px = e % LX, py = e / LX;
+                const int32_t gx = wrap_index(x0 + px - HL, nx, a.bc[0]);
+                const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - HL, ny, a.bc[1]) : 0;
+                const int32_t gi = gy * nx + gx;
 #pragma unroll
-        for (int q = 0; q < NF; ++q) {
-            const double ds = 0.5 * wd * gs[q];
-            const double gL = 0.5 * (jl[q] + s * w[q]) - (selL ? ds : 0.0);
-            const double gR = 0.5 * (jr[q] - s * w[q]) - (selL ? 0.0 : ds);
-            sg[(2 * q) * NFACES + f] = gL;
-            sg[(2 * q + 1) * NFACES + f] = gR;
+                for (int q = 0; q < NF; ++q) vl[k][q] = lam[q * a.cells + gi];
+            }
         }
-        scode[f] = codes;
+#pragma unroll
+        for (int k = 0; k < UPT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if ((k + 1) * NT <= UC || e < UC) {
+#pragma unroll
+                for (int q = 0; q < NF; ++q) su[q * UC + e] = vu[k][q];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < LPT; ++k) {
+            const int e = threadIdx.x + k * NT;
+            if ((k + 1) * NT <= LC || e < LC) {
+#pragma unroll
+                for (int q = 0; q < NF; ++q) sl[q * LC + e] = vl[k][q];
+            }
+        }
     }
     __syncthreads();
 
-    // gather J^T lam per cell, then the reverse stage combination
+    // one axis at a time: its faces' (g_L, g_R, codes) into LDS, then every cell gathers the
+    // axis's four (MUSCL) or two faces; axis 0 is added before axis 1, as in eq. 2.1
+    double jt[T::CPT][NF];
+#pragma unroll
+    for (int k = 0; k < T::CPT; ++k)
+#pragma unroll
+        for (int q = 0; q < NF; ++q) jt[k][q] = 0.0;
+#pragma unroll
+    for (int nd = 0; nd < DIM; ++nd) {
+        const int nfaces = (nd == 0) ? NFX : NFY;
+        for (int f = threadIdx.x; f < nfaces; f += NT) {
+            int fx, fy;   // face between (right cell) and (right cell - e_nd), tile-local
+            if (nd == 0) {
+                fx = f % EXN - R;          // right-cell x offset from x0, in [-R, BX + R]
+                fy = f / EXN;
+            } else {
+                fx = f % BX;
+                fy = f / BX - R;
+            }
+            const int cu = ((DIM >= 2 ? fy + HU : 0)) * UX + (fx + HU);
+            const int su_stride = (nd == 0) ? 1 : UX;
+            const int cl = ((DIM >= 2 ? fy + HL : 0)) * LX + (fx + HL);
+            const int sl_stride = (nd == 0) ? 1 : LX;
+            double UL[NF], UR[NF], w[NF];
+            int codes = 0;
+            const double inv = (nd == 0) ? a.ph.inv_dx[0] : a.ph.inv_dx[1];
+#pragma unroll
+            for (int q = 0; q < NF; ++q) {
+                const double* sp = su + q * UC + cu;
+                const double ua = sp[-su_stride], ub = sp[0];
+                if (RECON == REC_MUSCL) {
+                    const double uam = sp[-2 * su_stride], ubp = sp[su_stride];
+                    const int cL = minmod_code(ua - uam, ub - ua);
+                    const int cR = minmod_code(ub - ua, ubp - ub);
+                    codes |= (cL | (cR << 2)) << (4 * q);
+                    UL[q] = ua + (0.5 * minmod(ua - uam, ub - ua));
+                    UR[q] = ub - (0.5 * minmod(ub - ua, ubp - ub));
+                } else {
+                    UL[q] = ua;
+                    UR[q] = ub;
+                }
+                const double* l = sl + q * LC + cl;
+                w[q] = inv * (l[0] - l[-sl_stride]);
+            }
+            const EulerPrim<DIM> pl = euler_prim<DIM>(UL, a.ph);
+            const EulerPrim<DIM> pr = euler_prim<DIM>(UR, a.ph);
+            const double sL = fabs(pick<DIM>(pl.u, nd)) + pl.c;
+            const double sR = fabs(pick<DIM>(pr.u, nd)) + pr.c;
+            const bool selL = sL > sR;
+            const double s = selL ? sL : sR;
+            double jl[NF], jr[NF], gs[NF];
+            euler_flux_jt<DIM>(UL, pl, nd, w, a.ph, jl);
+            euler_flux_jt<DIM>(UR, pr, nd, w, a.ph, jr);
+            if (selL) speed_grad<DIM>(UL, pl, nd, a.ph, gs);
+            else speed_grad<DIM>(UR, pr, nd, a.ph, gs);
+            double wd = 0.0;
+#pragma unroll
+            for (int q = 0; q < NF; ++q) wd = wd + w[q] * (UR[q] - UL[q]);
+#pragma unroll
+            for (int q = 0; q < NF; ++q) {
+                const double ds = 0.5 * wd * gs[q];
+                const double gL = 0.5 * (jl[q] + s * w[q]) - (selL ? ds : 0.0);
+                const double gR = 0.5 * (jr[q] - s * w[q]) - (selL ? 0.0 : ds);
+                sg[(2 * q) * MAXF + f] = gL;
+                sg[(2 * q + 1) * MAXF + f] = gR;
+            }
+            scode[f] = codes;
+        }
+        __syncthreads();
+
+#pragma unroll
+        for (int k = 0; k < T::CPT; ++k) {
+            const int c = threadIdx.x + k * NT;
+            if (c >= T::CELLS) break;
+            const int cx = c % BX, cy = c / BX;
+            // face index (within this axis) with right cell at tile offset o + shift along nd
+            auto face = [&](int shift) -> int {
+                if (nd == 0) return cy * EXN + (cx + shift + R);
+                return (cy + shift + R) * BX + cx;
+            };
+#pragma unroll
+            for (int q = 0; q < NF; ++q) {
+                double v = jt[k][q];
+                if (RECON == REC_MUSCL) {
+                    {   // face c - 3/2 (right cell c - 1): this cell is b + 1
+                        const int f = face(-1);
+                        const int cR = (scode[f] >> (4 * q + 2)) & 3;
+                        v = v + sg[(2 * q + 1) * MAXF + f] * ((cR == 2) ? -0.5 : 0.0);
+                    }
+                    {   // face c - 1/2 (right cell c): this cell is b
+                        const int f = face(0);
+                        const int cL = (scode[f] >> (4 * q)) & 3;
+                        const int cR = (scode[f] >> (4 * q + 2)) & 3;
+                        v = v + sg[(2 * q) * MAXF + f] * ((cL == 2) ? 0.5 : 0.0);
+                        v = v + sg[(2 * q + 1) * MAXF + f] * ((cR == 1) ? 0.5 : ((cR == 2) ? 1.5 : 1.0));
+                    }
+                    {   // face c + 1/2 (right cell c + 1): this cell is a
+                        const int f = face(1);
+                        const int cL = (scode[f] >> (4 * q)) & 3;
+                        const int cR = (scode[f] >> (4 * q + 2)) & 3;
+                        v = v + sg[(2 * q) * MAXF + f] * ((cL == 1) ? 1.5 : ((cL == 2) ? 0.5 : 1.0));
+                        v = v + sg[(2 * q + 1) * MAXF + f] * ((cR == 1) ? 0.5 : 0.0);
+                    }
+                    {   // face c + 3/2 (right cell c + 2): this cell is a - 1
+                        const int f = face(2);
+                        const int cL = (scode[f] >> (4 * q)) & 3;
+                        v = v + sg[(2 * q) * MAXF + f] * ((cL == 1) ? -0.5 : 0.0);
+                    }
+                } else {
+                    v = v + sg[(2 * q + 1) * MAXF + face(0)];   // face c - 1/2: g_R
+                    v = v + sg[(2 * q) * MAXF + face(1)];       // face c + 1/2: g_L
+                }
+                jt[k][q] = v;
+            }
+        }
+        if (nd + 1 < DIM) __syncthreads();   // the next axis overwrites sg
+    }
+
+    // the reverse stage combination
     double* prev = a.prev + sbase;
     double* acc = a.acc + sbase;
 #pragma unroll
@@ -212,57 +298,12 @@ adjoint_stage_kernel(const AdjArgs a)
         const int cx = c % BX, cy = c / BX;
         const int32_t gx = x0 + cx, gy = y0 + cy;
         if (gx >= nx || gy >= ny) continue;
-        const int64_t gi = (int64_t)gy * nx + gx;
-        double jt[NF];
-#pragma unroll
-        for (int q = 0; q < NF; ++q) jt[q] = 0.0;
-#pragma unroll
-        for (int nd = 0; nd < DIM; ++nd) {
-            // face index with right cell at tile offset o along nd (o = cx or cy + shift)
-            auto face = [&](int shift) -> int {
-                if (nd == 0) return cy * EXN + (cx + shift + R);
-                return NFX + (cy + shift + R) * BX + cx;
-            };
-#pragma unroll
-            for (int q = 0; q < NF; ++q) {
-                double v = jt[q];
-                if (RECON == REC_MUSCL) {
-                    {   // face c - 3/2 (right cell c - 1): this cell is b + 1
-                        const int f = face(-1);
-                        const int cR = (scode[f] >> (4 * q + 2)) & 3;
-                        v = v + sg[(2 * q + 1) * NFACES + f] * ((cR == 2) ? -0.5 : 0.0);
-                    }
-                    {   // face c - 1/2 (right cell c): this cell is b
-                        const int f = face(0);
-                        const int cL = (scode[f] >> (4 * q)) & 3;
-                        const int cR = (scode[f] >> (4 * q + 2)) & 3;
-                        v = v + sg[(2 * q) * NFACES + f] * ((cL == 2) ? 0.5 : 0.0);
-                        v = v + sg[(2 * q + 1) * NFACES + f] * ((cR == 1) ? 0.5 : ((cR == 2) ? 1.5 : 1.0));
-                    }
-                    {   // face c + 1/2 (right cell c + 1): this cell is a
-                        const int f = face(1);
-                        const int cL = (scode[f] >> (4 * q)) & 3;
-                        const int cR = (scode[f] >> (4 * q + 2)) & 3;
-                        v = v + sg[(2 * q) * NFACES + f] * ((cL == 1) ? 1.5 : ((cL == 2) ? 0.5 : 1.0));
-                        v = v + sg[(2 * q + 1) * NFACES + f] * ((cR == 1) ? 0.5 : 0.0);
-                    }
-                    {   // face c + 3/2 (right cell c + 2): this cell is a - 1
-                        const int f = face(2);
-                        const int cL = (scode[f] >> (4 * q)) & 3;
-                        v = v + sg[(2 * q) * NFACES + f] * ((cL == 1) ? -0.5 : 0.0);
-                    }
-                } else {
-                    v = v + sg[(2 * q + 1) * NFACES + face(0)];   // face c - 1/2: g_R
-                    v = v + sg[(2 * q) * NFACES + face(1)];       // face c + 1/2: g_L
-                }
-                jt[q] = v;
-            }
-        }
+        const int32_t gi = gy * nx + gx;
         const int cl = ((DIM >= 2 ? cy + HL : 0)) * LX + (cx + HL);
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
             const double lq = sl[q * LC + cl];
-            const double contrib = a.beta * (lq + a.dt * jt[q]);
+            const double contrib = a.beta * (lq + a.dt * jt[k][q]);
             const int64_t o = q * a.cells + gi;
             if (a.mode == 2) {
                 prev[o] = acc[o] + contrib;

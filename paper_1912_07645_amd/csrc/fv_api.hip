@@ -816,14 +816,16 @@ extern "C" fv_status fv_stats_create(const fv_solver* s, int32_t max_h, fv_stats
     st->chunk = 64;
     const size_t field = sizeof(double) * st->nq * s->cells;
     const size_t lags = sizeof(double) * st->nq * std::max(max_h, 1);
-    const int nblk = sf_blocks_per_field(s->cells);
+    const int32_t n32[3] = {(int32_t)s->grid.n[0], (int32_t)s->grid.n[1], (int32_t)s->grid.n[2]};
+    const int nblk = max_h > 0 ? sf_blocks_per_field(s->grid.dim, n32) : 0;
     bool ok = hipMalloc((void**)&st->mean, field) == hipSuccess &&
               hipMalloc((void**)&st->m2, field) == hipSuccess &&
               hipMalloc((void**)&st->s2mean, lags) == hipSuccess &&
               hipMalloc((void**)&st->s2m2, lags) == hipSuccess;
     if (ok && max_h > 0)
         ok = hipMalloc((void**)&st->qbuf, field * st->chunk) == hipSuccess &&
-             hipMalloc((void**)&st->partial, sizeof(double) * st->chunk * st->nq * max_h * nblk) == hipSuccess;
+             hipMalloc((void**)&st->partial,
+                       sizeof(double) * st->chunk * st->nq * max_h * (nblk + 1)) == hipSuccess;
     if (!ok) {
         fv_stats_destroy(st);
         return fail(FV_ENOMEM, "statistics allocation failed");
@@ -864,18 +866,20 @@ extern "C" fv_status fv_stats_accumulate(fv_stats* st, const double* state, int6
     hipStream_t str = s->stream;
     const bool euler = s->eq.kind == FV_EQ_EULER;
     const int64_t per = (int64_t)s->nf * s->cells;
-    const int nblk = sf_blocks_per_field(s->cells);
     int32_t n32[3] = {(int32_t)s->grid.n[0], (int32_t)s->grid.n[1], (int32_t)s->grid.n[2]};
+    const int nblk = st->max_h > 0 ? sf_blocks_per_field(s->grid.dim, n32) : 0;
     const double denom = (double)s->grid.dim * (double)s->cells;
     for (int64_t b0 = 0; b0 < batch; b0 += st->chunk) {
         const int32_t nb = (int32_t)std::min<int64_t>(st->chunk, batch - b0);
         const double* chunk = state + b0 * per;
-        launch_welford(s->nf, euler, chunk, s->cells, nb, st->count, st->mean, st->m2, str);
+        launch_welford(s->nf, euler, chunk, s->cells, nb, st->count, st->mean, st->m2,
+                       st->max_h > 0 ? st->qbuf : nullptr, str);
         if (st->max_h > 0) {
-            launch_quantities(s->nf, euler, chunk, s->cells, nb, st->qbuf, str);
             launch_sf_partial(st->qbuf, s->grid.dim, n32, st->nq, st->max_h, nb, st->partial, str);
-            launch_sf_welford(st->partial, st->nq, st->max_h, nblk, nb, st->count, denom, st->s2mean,
-                              st->s2m2, str);
+            // the per-sample values follow the partials in the same allocation
+            double* xs = st->partial + (size_t)st->chunk * st->nq * st->max_h * nblk;
+            launch_sf_welford(st->partial, st->nq, st->max_h, nblk, nb, st->count, denom, xs,
+                              st->s2mean, st->s2m2, str);
         }
         HIP_TRY(hipGetLastError());
         st->count += nb;

@@ -28,16 +28,17 @@ void launch_welford_diff(int nf, bool euler, const double* fine, const double* c
                          double* m2, hipStream_t s);
 void launch_mlmc_combine(const CombineArgs& a, double* out, hipStream_t s);
 
-int sf_blocks_per_field(int64_t cells);
+// Workgroups per (sample, quantity) of the structure-function pass.
+int sf_blocks_per_field(int32_t dim, const int32_t n[3]);
+// qout (may be null): also write the quantity fields of the batch, [sample][quantity][cells].
 void launch_welford(int nf, bool euler, const double* state, int64_t cells, int32_t batch,
-                    int64_t count0, double* mean, double* m2, hipStream_t s);
-void launch_quantities(int nf, bool euler, const double* state, int64_t cells, int32_t batch,
-                       double* q, hipStream_t s);
+                    int64_t count0, double* mean, double* m2, double* qout, hipStream_t s);
 void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t nq, int32_t max_h,
                        int32_t batch, double* partial, hipStream_t s);
+// x: scratch of batch * nq * max_h doubles (S_q(h) of each sample of the chunk).
 void launch_sf_welford(const double* partial, int32_t nq, int32_t max_h, int32_t nblk,
-                       int32_t batch, int64_t count0, double denom, double* s2mean, double* s2m2,
-                       hipStream_t s);
+                       int32_t batch, int64_t count0, double denom, double* x, double* s2mean,
+                       double* s2m2, hipStream_t s);
 void launch_variance(const double* m2, int64_t n, double count, double* var, hipStream_t s);
 void launch_fill_zero(double* p, int64_t n, hipStream_t s);
 

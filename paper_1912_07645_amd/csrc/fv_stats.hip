@@ -8,11 +8,13 @@
 namespace fvk {
 
 // Per-cell Welford update over the samples of one batch, in sample order. One thread per
-// cell keeps the running moments of every quantity in registers.
+// cell keeps the running moments of every quantity in registers. With qout, the quantity
+// fields of the samples are also written there ([sample][quantity][cells]) for the
+// structure functions, so the state is read once.
 template <int NF, bool EULER>
 __global__ void __launch_bounds__(256)
 welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, int64_t count0,
-               double* __restrict__ mean, double* __restrict__ m2)
+               double* __restrict__ mean, double* __restrict__ m2, double* __restrict__ qout)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
@@ -32,6 +34,11 @@ welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, i
 #pragma unroll
             for (int q = 1; q < NF - 1; ++q) x[q] = x[q] * ir;
         }
+        if (qout) {
+            double* Q = qout + (int64_t)b * NF * cells + c;
+#pragma unroll
+            for (int q = 0; q < NF; ++q) Q[q * cells] = x[q];
+        }
         const double n = (double)(count0 + b + 1);
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
@@ -47,108 +54,187 @@ welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, i
     }
 }
 
-// Quantity fields q[b][quantity][cells] of a chunk of samples (elementwise).
-template <int NF, bool EULER>
-__global__ void quantities_kernel(const double* __restrict__ state, int64_t cells, int32_t batch,
-                                  double* __restrict__ q)
+// Structure-function partial sums. Every line of cells along every axis is cut into segments
+// of kSfSeg cells; a thread takes kSfSegsPerThread segments and, lag after lag, accumulates
+// sum_cells (q(x + h e) - q(x))^2 over their cells. The values q(x + h e) of a segment form a
+// window that slides by one cell per lag, so each lag costs one new load per segment instead
+// of one per cell. Segments along y and z are dealt so that neighbouring lanes take
+// neighbouring lines (coalesced loads); along x, neighbouring lanes take neighbouring
+// segments of a row. Lags are taken kSfLagChunk at a time (register accumulators); each is
+// summed over the workgroup in a fixed order (wavefront shuffles, then the four wavefronts in
+// order) into one partial per workgroup. Grid: (workgroups per field, quantity, sample).
+constexpr int kSfSeg = 8;
+constexpr int kSfLagChunk = 16;
+constexpr int kSfThreads = 256;
+constexpr int kSfSegsPerThread = 4;
+
+struct SfGeom {
+    int32_t n[3];          // grid
+    int32_t dim;
+    int64_t lines[3];      // lines along axis d: cells / n[d]
+    int64_t segs[3];       // segments per line along axis d
+    int64_t items[4];      // first segment of axis d (items[dim] = total)
+};
+
+static SfGeom sf_geom(int32_t dim, const int32_t n[3])
 {
-    const int64_t total = cells * batch;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = i / cells, c = i % cells;
-        const double* U = state + b * NF * cells + c;
-        double* Q = q + b * NF * cells + c;
-        if (EULER) {
-            const double ir = 1.0 / U[0];
-            Q[0] = U[0];
-#pragma unroll
-            for (int k = 1; k < NF - 1; ++k) Q[k * cells] = U[k * cells] * ir;
-            Q[(NF - 1) * cells] = U[(NF - 1) * cells];
-        } else {
-#pragma unroll
-            for (int k = 0; k < NF; ++k) Q[k * cells] = U[k * cells];
-        }
+    SfGeom g{};
+    g.dim = dim;
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    int64_t acc = 0;
+    for (int d = 0; d < 3; ++d) {
+        g.n[d] = n[d];
+        g.lines[d] = cells / n[d];
+        g.segs[d] = (n[d] + kSfSeg - 1) / kSfSeg;
+        g.items[d] = acc;
+        if (d < dim) acc += g.lines[d] * g.segs[d];
     }
+    g.items[dim] = acc;
+    for (int d = dim + 1; d < 4; ++d) g.items[d] = acc;
+    return g;
 }
 
-// Partial sums over a block of cells of sum_axes (q(x + h e) - q(x))^2 for HC lags
-// h = h0 .. h0 + HC - 1. Grid: (blocks per field, quantity, sample).
-constexpr int kSfCellsPerBlock = 2048;
-constexpr int kSfLags = 8;
-
-__global__ void __launch_bounds__(256)
-sf_partial_kernel(const double* __restrict__ q, int32_t dim, int32_t nx, int32_t ny, int32_t nz,
-                  int32_t nq, int32_t max_h, int32_t nblk, double* __restrict__ partial)
+__device__ __forceinline__ double wave_sum(double v)
 {
-    __shared__ double red[256];
-    const int64_t cells = (int64_t)nx * ny * nz;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Segment `item`: first cell base + x0 * stride along a line of nd cells, len cells in it.
+struct SfSeg {
+    int64_t base, stride;
+    int32_t x0, nd, len;
+};
+
+__device__ __forceinline__ SfSeg sf_segment(const SfGeom& geo, int64_t item)
+{
+    SfSeg sg;
+    if (item >= geo.items[geo.dim]) {   // no segment: nothing is read or added
+        sg.base = 0; sg.stride = 1; sg.x0 = 0; sg.nd = 1; sg.len = 0;
+        return sg;
+    }
+    int d = 0;
+    if (item >= geo.items[1]) d = 1;
+    if (item >= geo.items[2]) d = 2;
+    const int64_t local = item - geo.items[d];
+    sg.nd = geo.n[d];
+    if (d == 0) {   // lanes along a row: item = line * segs + segment
+        const int64_t line = local / geo.segs[0];
+        sg.x0 = (int32_t)(local % geo.segs[0]) * kSfSeg;
+        sg.base = line * geo.n[0];
+        sg.stride = 1;
+    } else {        // lanes across lines: item = segment * lines + line
+        const int64_t line = local % geo.lines[d];
+        sg.x0 = (int32_t)(local / geo.lines[d]) * kSfSeg;
+        if (d == 1) {
+            const int64_t xi = line % geo.n[0], zi = line / geo.n[0];
+            sg.base = zi * geo.n[0] * geo.n[1] + xi;
+            sg.stride = geo.n[0];
+        } else {
+            sg.base = line;
+            sg.stride = (int64_t)geo.n[0] * geo.n[1];
+        }
+    }
+    sg.len = (sg.nd - sg.x0 < kSfSeg) ? sg.nd - sg.x0 : kSfSeg;
+    return sg;
+}
+
+__global__ void __launch_bounds__(kSfThreads)
+sf_partial_kernel(const double* __restrict__ q, const SfGeom geo, int32_t nq, int32_t max_h,
+                  int32_t nblk, double* __restrict__ partial)
+{
+    __shared__ double red[kSfThreads / 64][kSfLagChunk];
+    const int64_t cells = (int64_t)geo.n[0] * geo.n[1] * geo.n[2];
     const int blk = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
     const double* Q = q + ((int64_t)b * nq + qi) * cells;
-    const int64_t c0 = (int64_t)blk * kSfCellsPerBlock;
-    for (int h0 = 1; h0 <= max_h; h0 += kSfLags) {
-        double acc[kSfLags];
+    const int64_t item0 = (int64_t)blk * kSfThreads * kSfSegsPerThread + threadIdx.x;
+
+    for (int h0 = 1; h0 <= max_h; h0 += kSfLagChunk) {
+        double acc[kSfLagChunk];
 #pragma unroll
-        for (int l = 0; l < kSfLags; ++l) acc[l] = 0.0;
-        for (int64_t c = c0 + threadIdx.x; c < c0 + kSfCellsPerBlock && c < cells; c += 256) {
-            const int32_t i = (int32_t)(c % nx);
-            const int32_t j = (int32_t)((c / nx) % ny);
-            const int32_t k = (int32_t)(c / ((int64_t)nx * ny));
-            const double v = Q[c];
-            for (int d = 0; d < dim; ++d) {
+        for (int l = 0; l < kSfLagChunk; ++l) acc[l] = 0.0;
+        for (int j = 0; j < kSfSegsPerThread; ++j) {
+            const SfSeg sg = sf_segment(geo, item0 + (int64_t)j * kSfThreads);
+            if (sg.len == 0) continue;
+            // base values q(x0 + r) (positions past the line wrap, and are masked)
+            double v0[kSfSeg], w[kSfSeg];
+            int32_t p = sg.x0;
 #pragma unroll
-                for (int l = 0; l < kSfLags; ++l) {
-                    const int h = h0 + l;
-                    if (h > max_h) break;
-                    int64_t c2;
-                    if (d == 0) {
-                        int32_t i2 = i + h; if (i2 >= nx) i2 -= nx;
-                        c2 = c - i + i2;
-                    } else if (d == 1) {
-                        int32_t j2 = j + h; if (j2 >= ny) j2 -= ny;
-                        c2 = c + (int64_t)(j2 - j) * nx;
-                    } else {
-                        int32_t k2 = k + h; if (k2 >= nz) k2 -= nz;
-                        c2 = c + (int64_t)(k2 - k) * nx * ny;
-                    }
-                    const double diff = Q[c2] - v;
-                    acc[l] = acc[l] + (diff * diff);
+            for (int r = 0; r < kSfSeg; ++r) {
+                v0[r] = Q[sg.base + p * sg.stride];
+                p = (p + 1 == sg.nd) ? 0 : p + 1;
+            }
+            // window w[r] = q(x0 + r + h0)
+            p = sg.x0 + h0;
+            if (p >= sg.nd) p -= sg.nd;   // x0 < nd and h0 < nd
+#pragma unroll
+            for (int r = 0; r < kSfSeg; ++r) {
+                w[r] = Q[sg.base + p * sg.stride];
+                if (r + 1 < kSfSeg) p = (p + 1 == sg.nd) ? 0 : p + 1;
+            }
+#pragma unroll
+            for (int l = 0; l < kSfLagChunk; ++l) {
+                double a = acc[l];
+#pragma unroll
+                for (int r = 0; r < kSfSeg; ++r) {
+                    const double df = w[r] - v0[r];
+                    a = (r < sg.len) ? __builtin_fma(df, df, a) : a;
+                }
+                acc[l] = a;
+                if (l + 1 < kSfLagChunk) {   // slide the window by one cell
+#pragma unroll
+                    for (int r = 0; r + 1 < kSfSeg; ++r) w[r] = w[r + 1];
+                    p = (p + 1 == sg.nd) ? 0 : p + 1;
+                    w[kSfSeg - 1] = (h0 + l + 1 <= max_h) ? Q[sg.base + p * sg.stride] : 0.0;
                 }
             }
         }
-        // fixed-shape tree over the 256 threads, lag by lag
-        for (int l = 0; l < kSfLags && h0 + l <= max_h; ++l) {
-            red[threadIdx.x] = acc[l];
-            __syncthreads();
-            for (int s = 128; s > 0; s >>= 1) {
-                if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
-                __syncthreads();
-            }
-            if (threadIdx.x == 0)
-                partial[(((int64_t)b * nq + qi) * max_h + (h0 + l - 1)) * nblk + blk] = red[0];
-            __syncthreads();
+        // workgroup sums of the chunk's lags, in a fixed order
+#pragma unroll
+        for (int l = 0; l < kSfLagChunk; ++l) {
+            const double ws = wave_sum(acc[l]);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][l] = ws;
         }
+        __syncthreads();
+        if (threadIdx.x < kSfLagChunk && h0 + (int)threadIdx.x <= max_h) {
+            double s = red[0][threadIdx.x];
+#pragma unroll
+            for (int wv = 1; wv < kSfThreads / 64; ++wv) s = s + red[wv][threadIdx.x];
+            partial[(((int64_t)b * nq + qi) * max_h + (h0 + threadIdx.x - 1)) * nblk + blk] = s;
+        }
+        __syncthreads();
     }
 }
 
-// Sum the partials of each (sample, quantity, lag) in block order, normalise, and update
-// the moments over samples in sample order. One thread per (quantity, lag).
-__global__ void sf_welford_kernel(const double* __restrict__ partial, int32_t nq, int32_t max_h,
-                                  int32_t nblk, int32_t batch, int64_t count0, double denom,
-                                  double* __restrict__ s2mean, double* __restrict__ s2m2)
+// S_q(h) of every sample of the chunk: the workgroup partials of (sample, quantity, lag)
+// summed in workgroup order and normalised. One thread per (sample, quantity, lag).
+__global__ void sf_sum_kernel(const double* __restrict__ partial, int32_t n_out, int32_t nblk,
+                              double denom, double* __restrict__ x)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nq * max_h) return;
-    const int qi = t / max_h, h = t % max_h;
+    if (t >= n_out) return;
+    const double* p = partial + (int64_t)t * nblk;
+    double s = p[0];
+    for (int k = 1; k < nblk; ++k) s = s + p[k];
+    x[t] = s / denom;
+}
+
+// Moments over samples of S_q(h), in sample order. One thread per (quantity, lag).
+__global__ void sf_welford_kernel(const double* __restrict__ x, int32_t nq, int32_t max_h,
+                                  int32_t batch, int64_t count0, double* __restrict__ s2mean,
+                                  double* __restrict__ s2m2)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nt = nq * max_h;
+    if (t >= nt) return;
     double mu = s2mean[t], s2 = s2m2[t];
     for (int32_t b = 0; b < batch; ++b) {
-        const double* p = partial + (((int64_t)b * nq + qi) * max_h + h) * nblk;
-        double s = p[0];
-        for (int k = 1; k < nblk; ++k) s = s + p[k];
-        const double x = s / denom;
+        const double v = x[(int64_t)b * nt + t];
         const double n = (double)(count0 + b + 1);
-        const double delta = x - mu;
+        const double delta = v - mu;
         mu = mu + (delta / n);
-        s2 = s2 + (delta * (x - mu));
+        s2 = s2 + (delta * (v - mu));
     }
     s2mean[t] = mu;
     s2m2[t] = s2;
@@ -269,62 +355,50 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n)
         p[i] = 0.0;
 }
 
-int sf_blocks_per_field(int64_t cells)
+int sf_blocks_per_field(int32_t dim, const int32_t n[3])
 {
-    return (int)((cells + kSfCellsPerBlock - 1) / kSfCellsPerBlock);
+    const SfGeom g = sf_geom(dim, n);
+    const int64_t per = (int64_t)kSfThreads * kSfSegsPerThread;
+    return (int)((g.items[dim] + per - 1) / per);
 }
 
 template <int NF, bool EULER>
 static void welford_launch(const double* state, int64_t cells, int32_t batch, int64_t count0,
-                           double* mean, double* m2, hipStream_t s)
+                           double* mean, double* m2, double* qout, hipStream_t s)
 {
     const unsigned nb = (unsigned)((cells + 255) / 256);
     hipLaunchKernelGGL((welford_kernel<NF, EULER>), dim3(nb), dim3(256), 0, s, state, cells,
-                       batch, count0, mean, m2);
-}
-
-template <int NF, bool EULER>
-static void quantities_launch(const double* state, int64_t cells, int32_t batch, double* q,
-                              hipStream_t s)
-{
-    hipLaunchKernelGGL((quantities_kernel<NF, EULER>), dim3(2048), dim3(256), 0, s, state, cells,
-                       batch, q);
+                       batch, count0, mean, m2, qout);
 }
 
 void launch_welford(int nf, bool euler, const double* state, int64_t cells, int32_t batch,
-                    int64_t count0, double* mean, double* m2, hipStream_t s)
+                    int64_t count0, double* mean, double* m2, double* qout, hipStream_t s)
 {
-    if (!euler) welford_launch<1, false>(state, cells, batch, count0, mean, m2, s);
-    else if (nf == 3) welford_launch<3, true>(state, cells, batch, count0, mean, m2, s);
-    else if (nf == 4) welford_launch<4, true>(state, cells, batch, count0, mean, m2, s);
-    else welford_launch<5, true>(state, cells, batch, count0, mean, m2, s);
-}
-
-void launch_quantities(int nf, bool euler, const double* state, int64_t cells, int32_t batch,
-                       double* q, hipStream_t s)
-{
-    if (!euler) quantities_launch<1, false>(state, cells, batch, q, s);
-    else if (nf == 3) quantities_launch<3, true>(state, cells, batch, q, s);
-    else if (nf == 4) quantities_launch<4, true>(state, cells, batch, q, s);
-    else quantities_launch<5, true>(state, cells, batch, q, s);
+    if (!euler) welford_launch<1, false>(state, cells, batch, count0, mean, m2, qout, s);
+    else if (nf == 3) welford_launch<3, true>(state, cells, batch, count0, mean, m2, qout, s);
+    else if (nf == 4) welford_launch<4, true>(state, cells, batch, count0, mean, m2, qout, s);
+    else welford_launch<5, true>(state, cells, batch, count0, mean, m2, qout, s);
 }
 
 void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t nq, int32_t max_h,
                        int32_t batch, double* partial, hipStream_t s)
 {
-    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
-    const int nblk = sf_blocks_per_field(cells);
-    hipLaunchKernelGGL(sf_partial_kernel, dim3(nblk, nq, batch), dim3(256), 0, s, q, dim, n[0], n[1],
-                       n[2], nq, max_h, nblk, partial);
+    const SfGeom g = sf_geom(dim, n);
+    const int nblk = sf_blocks_per_field(dim, n);
+    hipLaunchKernelGGL(sf_partial_kernel, dim3(nblk, nq, batch), dim3(kSfThreads), 0, s, q, g, nq,
+                       max_h, nblk, partial);
 }
 
 void launch_sf_welford(const double* partial, int32_t nq, int32_t max_h, int32_t nblk,
-                       int32_t batch, int64_t count0, double denom, double* s2mean, double* s2m2,
-                       hipStream_t s)
+                       int32_t batch, int64_t count0, double denom, double* x, double* s2mean,
+                       double* s2m2, hipStream_t s)
 {
+    const int n_out = batch * nq * max_h;
+    hipLaunchKernelGGL(sf_sum_kernel, dim3((n_out + 255) / 256), dim3(256), 0, s, partial, n_out,
+                       nblk, denom, x);
     const int t = nq * max_h;
-    hipLaunchKernelGGL(sf_welford_kernel, dim3((t + 63) / 64), dim3(64), 0, s, partial, nq, max_h,
-                       nblk, batch, count0, denom, s2mean, s2m2);
+    hipLaunchKernelGGL(sf_welford_kernel, dim3((t + 63) / 64), dim3(64), 0, s, x, nq, max_h, batch,
+                       count0, s2mean, s2m2);
 }
 
 void launch_variance(const double* m2, int64_t n, double count, double* var, hipStream_t s)

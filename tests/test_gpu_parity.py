@@ -317,6 +317,34 @@ def test_statistics_match_oracle():
                   what="S2 var")
 
 
+@pytest.mark.parametrize("dim,n,eq,H,B", [
+    (1, (37,), "advection", 20, 9),       # one line; segments end inside it; lags past n/2
+    (2, (29, 19), "euler", 18, 70),       # ragged along x and y, lags up to n_y - 1, two chunks
+    (3, (12, 10, 9), "euler", 8, 5),      # all three axes
+    (2, (16, 24), "burgers", 15, 3),      # whole segments, a scalar field
+])
+def test_structure_functions_match_oracle(dim, n, eq, H, B):
+    """S_q(h) for h = 1..H and its moments over samples against the oracle, on grids whose
+    lines end inside a segment, lags up to n - 1 on the shortest axis, every dimension."""
+    torch = torch_gpu()
+    from paper_1912_07645_amd import Stats
+    p = O.Problem(dim=dim, n=n, eq=eq, flux="rusanov", recon="first_order",
+                  integrator="forward_euler", vel=(0.7, -0.4, 0.3))
+    U0 = np.concatenate([_initial(p, 50 + b) for b in range((B + 1) // 2)])[:B]
+    note("structure functions", dim, n, eq, H, B)
+    st = Stats(solver_for(p), max_h=H)
+    st.accumulate(torch.from_numpy(np.ascontiguousarray(U0)).cuda())
+    out = st.read()
+    ref = O.Stats(p, max_h=H)
+    ref.accumulate(U0)
+    assert out["count"] == ref.n == B
+    assert_parity(out["mean"].cpu().numpy(), ref.mean, what="mean")
+    assert_parity(out["s2_mean"].cpu().numpy(), ref.s2(), bitwise=False, what="S2 mean")
+    if B > 1:
+        assert_parity(out["s2_var"].cpu().numpy(), ref.s2_variance(), tol=1e-10, bitwise=False,
+                      what="S2 var")
+
+
 def test_kh3d_full_size_sampled_cells():
     """3D KH at the full 512^3 size (one GPU's periodic subdomain, 5.4 GB per state): one
     full SSP-RK3 step on the GPU; sampled cells are recomputed by the oracle one by one from
