@@ -442,7 +442,7 @@ def measure(a, w, steps=None, warmup=None):
             "mc_sample_steps_per_s", "per_sample_launch_sample_steps_per_s",
             "batched_speedup_over_per_sample_launches", "stats_ms_for_batch")}
         out["batched_mc"]["config"] = mc["config"]["workload"]
-        adj = run_adjoint(argparse.Namespace(steps=1, warmup=1), WORKLOADS["adjoint"])
+        adj = run_adjoint(argparse.Namespace(steps=1, warmup=1, variant=None), WORKLOADS["adjoint"])
         out["adjoint"] = {k: adj[k] for k in ("forward_ms", "gradient_ms",
                                                "adjoint_over_forward_cost")}
         out["adjoint"]["config"] = adj["config"]["workload"]
