@@ -73,26 +73,39 @@ struct StageTile {
     static_assert(DIM >= 3 || BZ == 1, "2D tiles are flat");
 };
 
+// LDS layouts of the haloed state tile. LAY_FIELD: one block per conserved field,
+// [q][z][y][x]. LAY_ROW: the fields interleaved row by row, [z][y][q][x], so that the halo
+// rows of the y axis are whole contiguous blocks at both ends of the tile.
+enum { LAY_FIELD = 0, LAY_ROW = 1 };
+
+template <int NF, int PX, int PY, int PZ, int LAY>
+struct TileLayout {
+    static constexpr int QS = (LAY == LAY_FIELD) ? PX * PY * PZ : PX;   // field stride
+    static constexpr int RS = (LAY == LAY_FIELD) ? PX : NF * PX;        // y stride
+    static constexpr int PS = RS * PY;                                  // z stride
+};
+
 // One face with normal axis ND (compile-time): reconstruction from the LDS tile and the
 // numerical flux into F.
-template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int ND>
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int ND,
+          int LAY = LAY_FIELD>
 __device__ __forceinline__ void one_face(const double* su, const Phys& ph, int l, double* F)
 {
     using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
-    constexpr int NF = T::NF, G = T::G, PX = T::PX, PY = T::PY, PCELLS = T::PCELLS;
-    constexpr int NFACES = T::NFACES;
+    using TL = TileLayout<T::NF, T::PX, T::PY, T::PZ, LAY>;
+    constexpr int NF = T::NF, G = T::G;
     constexpr int GY = (DIM >= 2) ? G : 0, GZ = (DIM >= 3) ? G : 0;
     constexpr int EX = BX + (ND == 0), EY = BY + (ND == 1);
-    constexpr int STRIDE = (ND == 0) ? 1 : ((ND == 1) ? PX : PX * PY);
+    constexpr int STRIDE = (ND == 0) ? 1 : ((ND == 1) ? TL::RS : TL::PS);
     const int fx = l % EX;
     const int fy = (l / EX) % EY;
     const int fz = l / (EX * EY);
     // LDS index of the cell on the right of the face (the face is its "minus" side)
-    const int c = ((fz + GZ) * PY + (fy + GY)) * PX + (fx + G);
+    const int c = (fz + GZ) * TL::PS + (fy + GY) * TL::RS + (fx + G);
     double UL[NF], UR[NF];
 #pragma unroll
     for (int q = 0; q < NF; ++q) {
-        const double* s = su + q * PCELLS + c;
+        const double* s = su + q * TL::QS + c;
         if (RECON == REC_FIRST) {
             reconstruct<RECON>(0.0, s[-STRIDE], s[0], 0.0, UL[q], UR[q]);
         } else {
@@ -112,6 +125,32 @@ struct FaceList {
     static constexpr int PZN = (T::NFZ + 63) / 64 * 64;
     static constexpr int TOTAL = PXN + PYN + PZN;
     static constexpr int FPT = (TOTAL + NT - 1) / NT;   // faces per thread
+};
+
+// LDS plan of HOLD = 2 (2D, LAY_ROW tile): the y faces are computed first. Once every
+// thread has read the tile, the y halo rows (the first and last G rows, contiguous in
+// LAY_ROW) are dead; the x fluxes, [q][face], are written from the start of the low halo
+// rows, continue at the start of the high halo rows and run on past the tile, and the y
+// fluxes, [q][face], follow. The workgroup needs the tile plus its faces minus those rows.
+template <int DIM, int EQ, int RECON, int BX, int BY, int BZ, int NT>
+struct SplitFaces {
+    using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    static constexpr int NF = T::NF, NFX = T::NFX, NFY = T::NFY;
+    static constexpr int SU = NF * T::PCELLS;
+    static constexpr int LOW = T::G * NF * T::PX;            // low halo rows: [0, LOW)
+    static constexpr int HIGH = (BY + T::G) * NF * T::PX;    // high halo rows: [HIGH, SU)
+    static constexpr int YB = HIGH + NF * NFX - LOW;         // first y flux
+    static constexpr int LDS = YB + NF * NFY;
+    // LDS index of x flux j = q * NFX + face
+    __device__ static __forceinline__ int x_at(int j) { return j < LOW ? j : j + (HIGH - LOW); }
+    // the same for field q, with the branch resolved at compile time where q decides it
+    __device__ static __forceinline__ int x_at(int q, int face)
+    {
+        const int j = q * NFX + face;
+        if ((q + 1) * NFX <= LOW) return j;
+        if (q * NFX >= LOW) return j + (HIGH - LOW);
+        return x_at(j);
+    }
 };
 
 // Face pf of the padded list: F gets its flux, *slot its index in the unpadded list sf[q][f]
@@ -147,13 +186,36 @@ __device__ __forceinline__ void list_face(const double* su, const Phys& ph, int 
 // HOLD = 1: each thread keeps its fluxes in registers until every thread has finished
 // reading the state tile, then they are written over it (sf aliases su): the workgroup
 // needs max(state tile, faces) of LDS instead of their sum, so more workgroups fit a CU.
+// HOLD = 2: y faces, then x faces written over the dead y halo rows (SplitFaces).
 template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD>
 __device__ __forceinline__ void tile_faces(const double* su, double* sf, const Phys& ph)
 {
     using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
     using L = FaceList<DIM, EQ, RECON, BX, BY, BZ, NT>;
     constexpr int NF = T::NF, NFACES = T::NFACES;
-    if constexpr (!HOLD) {
+    if constexpr (HOLD == 2) {
+        static_assert(DIM == 2, "split faces are for 2D tiles");
+        using S = SplitFaces<DIM, EQ, RECON, BX, BY, BZ, NT>;
+        constexpr int NFX = T::NFX, NFY = T::NFY;
+        static_assert(NF * NFX >= S::LOW && S::YB >= S::SU, "x fluxes cover the low halo rows");
+        for (int pf = threadIdx.x; pf < L::PYN; pf += NT) {
+            double F[NF];
+            one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, 1, LAY_ROW>(su, ph, pf < NFY ? pf : NFY - 1, F);
+            if (pf < NFY) {
+#pragma unroll
+                for (int q = 0; q < NF; ++q) sf[S::YB + q * NFY + pf] = F[q];
+            }
+        }
+        __syncthreads();   // the y halo rows are dead from here on
+        for (int pf = threadIdx.x; pf < L::PXN; pf += NT) {
+            double F[NF];
+            one_face<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, 0, LAY_ROW>(su, ph, pf < NFX ? pf : NFX - 1, F);
+            if (pf < NFX) {
+#pragma unroll
+                for (int q = 0; q < NF; ++q) sf[S::x_at(q, pf)] = F[q];
+            }
+        }
+    } else if constexpr (!HOLD) {
         for (int pf = threadIdx.x; pf < L::TOTAL; pf += NT) {
             double F[NF];
             int slot;
@@ -231,10 +293,13 @@ stage_kernel(const StageArgs args)
     constexpr int NFX = T::NFX, NFY = T::NFY, NFACES = T::NFACES;
     constexpr int GY = (DIM >= 2) ? G : 0, GZ = (DIM >= 3) ? G : 0;
     constexpr int SU = NF * PCELLS, SF = NF * NFACES;
-    constexpr int LDS = HOLD ? (SU > SF ? SU : SF) : SU + SF;
+    constexpr int LAY = (HOLD == 2) ? LAY_ROW : LAY_FIELD;
+    using TL = TileLayout<NF, PX, PY, T::PZ, LAY>;
+    using S = SplitFaces<DIM, EQ, RECON, BX, BY, BZ, NT>;
+    constexpr int LDS = (HOLD == 1) ? (SU > SF ? SU : SF) : ((HOLD == 2) ? S::LDS : SU + SF);
     __shared__ double lds[LDS];
     double* su = lds;
-    double* sf = HOLD ? lds : lds + SU;
+    double* sf = (HOLD != 0) ? lds : lds + SU;
 
     const int64_t blk = xcd_remap(blockIdx.x, args.nblocks);
     const int gi = find_group(args.g, args.ngroups, blk);
@@ -291,7 +356,7 @@ stage_kernel(const StageArgs args)
         // U^n of the thread's cells (stages >= 2), requested with the tile so that its
         // latency hides behind the faces (not where the fluxes are held in registers: there
         // the extra registers cost more than the wait)
-        if (!HOLD && args.use_un) {
+        if (HOLD != 1 && args.use_un) {
 #pragma unroll
             for (int k = 0; k < CPT; ++k) {
                 if (cell_ok[k]) {
@@ -304,8 +369,11 @@ stage_kernel(const StageArgs args)
         for (int k = 0; k < LPT; ++k) {
             const int e = threadIdx.x + k * NT;
             if ((k + 1) * NT <= PCELLS || e < PCELLS) {
+                const int px = e % PX;
+                const int row = e / PX;   // z * PY + y
 #pragma unroll
-                for (int q = 0; q < NF; ++q) su[q * PCELLS + e] = v[k][q];
+                for (int q = 0; q < NF; ++q)
+                    su[(LAY == LAY_FIELD) ? q * PCELLS + e : row * TL::RS + q * TL::QS + px] = v[k][q];
             }
         }
     }
@@ -329,20 +397,28 @@ stage_kernel(const StageArgs args)
         const int cy = (c / BX) % BY;
         const int cz = c / (BX * BY);
         const int32_t gidx = cell_g[k];
-        const int lc = ((cz + GZ) * PY + (cy + GY)) * PX + (cx + G);
+        const int lc = (cz + GZ) * TL::PS + (cy + GY) * TL::RS + (cx + G);
         const int fxm = (cz * BY + cy) * (BX + 1) + cx;
         const int fym = NFX + (cz * (BY + 1) + cy) * BX + cx;
         const int fzm = NFX + NFY + (cz * BY + cy) * BX + cx;
         double out[NF];
 #pragma unroll
         for (int q = 0; q < NF; ++q) {
-            const double* F = sf + q * NFACES;
-            double acc = (F[fxm + 1] - F[fxm]) * g.ph.inv_dx[0];
-            if (DIM >= 2) acc = acc + ((F[fym + BX] - F[fym]) * g.ph.inv_dx[1]);
-            if (DIM >= 3) acc = acc + ((F[fzm + BX * BY] - F[fzm]) * g.ph.inv_dx[2]);
+            double acc;
+            if constexpr (HOLD == 2) {
+                const int fyl = cy * BX + cx;
+                const double* Fy = sf + S::YB + q * NFY;
+                acc = (sf[S::x_at(q, fxm + 1)] - sf[S::x_at(q, fxm)]) * g.ph.inv_dx[0];
+                acc = acc + ((Fy[fyl + BX] - Fy[fyl]) * g.ph.inv_dx[1]);
+            } else {
+                const double* F = sf + q * NFACES;
+                acc = (F[fxm + 1] - F[fxm]) * g.ph.inv_dx[0];
+                if (DIM >= 2) acc = acc + ((F[fym + BX] - F[fym]) * g.ph.inv_dx[1]);
+                if (DIM >= 3) acc = acc + ((F[fzm + BX * BY] - F[fzm]) * g.ph.inv_dx[2]);
+            }
             const double rhs = -acc;
-            const double up = HOLD ? src[q * g.cells + gidx] : su[q * PCELLS + lc];
-            const double u0 = args.use_un ? (HOLD ? un[q * g.cells + gidx] : unr[k][q]) : up;
+            const double up = (HOLD == 1) ? src[q * g.cells + gidx] : su[q * TL::QS + lc];
+            const double u0 = args.use_un ? ((HOLD == 1) ? un[q * g.cells + gidx] : unr[k][q]) : up;
             out[q] = u0 + (beta * ((up - u0) + (dt * rhs)));
             dst[q * g.cells + gidx] = out[q];
         }
@@ -405,7 +481,9 @@ void launch_speed(const SpeedArgs& a, hipStream_t s)
                        kSpeedCellsPerBlock);
 }
 
-template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD = 1>
+// Default LDS plan: split faces in 2D, fluxes held in registers otherwise.
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT,
+          int HOLD = (DIM == 2) ? 2 : 1>
 constexpr StageKernel make_stage_kernel()
 {
     return StageKernel{&launch_stage<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, HOLD>,

@@ -147,8 +147,8 @@ def test_kh3d_small_bitwise():
 
 def test_2d_hot_variants_ragged_transmissive_batched():
     """2D WENO3 + HLLC on a ragged 70 x 83 grid with transmissive boundaries, a batch of four
-    samples: every tile variant (tiles, and y-marching strips whose last band and segment end
-    inside the grid) equals the oracle bit for bit."""
+    samples: every tile variant (16 x 15 and 32 x 15 tiles, each LDS plan; the last tile row and
+    column end inside the grid) equals the oracle bit for bit."""
     p = O.Problem(dim=2, n=(70, 83), eq="euler", flux="hllc", recon="weno3",
                   integrator="ssprk3", bc=("transmissive",) * 3)
     U0 = np.concatenate([_initial(p, 41 + b) for b in range(2)])
