@@ -161,9 +161,11 @@ fv_status fv_set_variant(fv_solver* solver, int32_t variant);
 fv_status fv_get_tile(const fv_solver* solver, int32_t* bx, int32_t* by, int32_t* bz,
                       int32_t* variant);
 
-/* Autotuner: time a few full steps of every variant on a copy of `state` (device,
- * [batch][fields][cells], not modified) and select the fastest; *chosen (may be NULL)
- * receives it. reps < 1 means 3 timed repetitions per variant. */
+/* Autotuner: after about 50 ms of untimed warm-up steps, time runs of 4 to 32 whole steps
+ * (about 8 ms each) of every variant on a copy of `state` (device, [batch][fields][cells],
+ * not modified) and select the one with the fastest median run; *chosen (may be NULL)
+ * receives it. reps < 1 means 3 timed runs per variant. Allocates a copy of the state for the
+ * duration of the call; on an error the variant selected before the call is kept. */
 fv_status fv_tune(fv_solver* solver, double* state, int64_t batch, int32_t reps,
                   int32_t* chosen);
 

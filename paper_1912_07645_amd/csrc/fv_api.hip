@@ -727,10 +727,10 @@ extern "C" fv_status fv_get_tile(const fv_solver* s, int32_t* bx, int32_t* by, i
     return FV_OK;
 }
 
-// Time one full step (all Runge--Kutta stages) of every tile variant on `state` for `batch`
-// samples and keep the fastest. The state is not modified: the tuner evolves a copy held in
-// the workspace's stage buffers. Results of every variant are bitwise identical, so the
-// choice affects speed only.
+// Time runs of whole steps (all Runge--Kutta stages) of every tile variant on `state` for
+// `batch` samples and keep the variant with the fastest median run. The state is not
+// modified: the tuner evolves a copy in a buffer of its own. Results of every variant are
+// bitwise identical, so the choice affects speed only.
 extern "C" fv_status fv_tune(fv_solver* s, double* state, int64_t batch, int32_t reps, int32_t* chosen)
 {
     if (!s || !state) return fail(FV_EINVAL, "NULL argument");
@@ -738,29 +738,48 @@ extern "C" fv_status fv_tune(fv_solver* s, double* state, int64_t batch, int32_t
     const int nv = fv_num_variants(s);
     if (reps < 1) reps = 3;
     HIP_TRY(hipSetDevice(s->device));
-    double best = 1e300;
-    int best_v = s->variant;
     const size_t state_bytes = sizeof(double) * (size_t)batch * s->nf * s->cells;
     double* scratch = nullptr;
     HIP_TRY(hipMalloc((void**)&scratch, align256(state_bytes) + sizeof(double) * batch));
     double* t = (double*)((char*)scratch + align256(state_bytes));
-    fv_status st = FV_OK;
+    // one run of n steps on a fresh copy of the state; its wall time in *sec
+    auto run = [&](int64_t n, double* sec) -> fv_status {
+        if (hipMemcpyAsync(scratch, state, state_bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
+            hipMemsetAsync(t, 0, sizeof(double) * batch, s->stream) != hipSuccess ||
+            hipStreamSynchronize(s->stream) != hipSuccess)
+            return fail(FV_EDEVICE, "tuner copy failed");
+        auto t0 = std::chrono::steady_clock::now();
+        fv_status e = fv_advance(s, scratch, batch, t, 1e300, 0.4, n, nullptr, nullptr);
+        auto t1 = std::chrono::steady_clock::now();
+        *sec = std::chrono::duration<double>(t1 - t0).count();
+        return e;
+    };
+    const int v0 = s->variant;
+    fv_status st = fv_set_variant(s, 0);
+    // Steps per timed run: about 8 ms of work (between 4 and 32), the same for every variant.
+    // Then about 50 ms of untimed steps, so that the clocks have left their idle state before
+    // the first variant is timed (timed cold, the first variant would lose).
+    double sec = 0.0;
+    int64_t nsteps = 4;
+    if (st == FV_OK) st = run(4, &sec);
+    if (st == FV_OK) {
+        nsteps = std::max<int64_t>(4, std::min<int64_t>(32, (int64_t)(8e-3 / std::max(sec / 4, 1e-9))));
+        double warm = 0.0;
+        while (st == FV_OK && warm < 50e-3) {
+            st = run(nsteps, &sec);
+            warm += sec;
+        }
+    }
+    double best = 1e300;
+    int best_v = v0;
     for (int v = 0; v < nv && st == FV_OK; ++v) {
         st = fv_set_variant(s, v);
         if (st) break;
+        // an untimed run loads the variant's kernels and captures its step graph
         std::vector<double> times;
         for (int r = 0; r < reps + 1 && st == FV_OK; ++r) {
-            if (hipMemcpyAsync(scratch, state, state_bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess ||
-                hipMemsetAsync(t, 0, sizeof(double) * batch, s->stream) != hipSuccess ||
-                hipStreamSynchronize(s->stream) != hipSuccess) {
-                st = fail(FV_EDEVICE, "tuner copy failed");
-                break;
-            }
-            auto t0 = std::chrono::steady_clock::now();
-            fv_status e = fv_advance(s, scratch, batch, t, 1e300, 0.4, 4, nullptr, nullptr);
-            auto t1 = std::chrono::steady_clock::now();
-            if (e != FV_OK) { st = e; break; }
-            if (r > 0) times.push_back(std::chrono::duration<double>(t1 - t0).count());
+            st = run(nsteps, &sec);
+            if (r > 0) times.push_back(sec);
         }
         if (st) break;
         std::sort(times.begin(), times.end());
@@ -768,7 +787,10 @@ extern "C" fv_status fv_tune(fv_solver* s, double* state, int64_t batch, int32_t
         if (med < best) { best = med; best_v = v; }
     }
     hipFree(scratch);
-    if (st) return st;
+    if (st) {
+        fv_set_variant(s, v0);
+        return st;
+    }
     st = fv_set_variant(s, best_v);
     if (chosen) *chosen = best_v;
     return st;

@@ -37,6 +37,18 @@ class MultilevelRun:
         """Pick the tile variant (shared by every grid: one launch covers them all) by timing
         `steps` multi-grid steps of copies of `states` per variant; returns the variant."""
         best, best_t = 0, None
+        # untimed steps first, so that the clocks have left their idle state before the first
+        # variant is timed
+        for s in self.solvers:
+            s.set_variant(0)
+        warm = 0.0
+        while warm < 0.05:
+            G = [U.clone() for U in states]
+            torch.cuda.synchronize(self.device)
+            t0 = time.perf_counter()
+            self.evolve(G, 1e30, cfl, max_steps=steps)
+            torch.cuda.synchronize(self.device)
+            warm += time.perf_counter() - t0
         for v in range(self.solvers[0].num_variants()):
             for s in self.solvers:
                 s.set_variant(v)
