@@ -10,6 +10,12 @@ C. H. Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014). Dra
 sample ``s`` under seed ``seed`` is ``mix64(seed + G * (s * 64 + j + 1))`` with the golden
 gamma ``G = 0x9E3779B97F4A7C15``; the top 53 bits give a uniform double in [0, 1).
 
+Quasi-Monte Carlo sample points come from a Sobol sequence (I. M. Sobol', 1967) built here
+from its definition: primitive polynomials over GF(2) enumerated by degree and value, unit
+initial direction numbers m_1 = ... = m_s = 1 (odd and below 2^k, as the construction
+requires), 32-bit direction numbers, and point n the XOR of the direction numbers of the set
+bits of n; the first coordinate is the van der Corput sequence in base 2.
+
 State layout (for every builder): float64, structure of arrays
 ``[batch][field][nz][ny][nx]`` with x fastest; Euler fields are (rho, m_x[, m_y[, m_z]], E).
 """
@@ -24,7 +30,8 @@ __all__ = [
     "mix64", "uniform_draws", "kh_coefficients", "kh3d_coefficients", "kh_delta",
     "sod_state", "riemann_state_1d", "kh2d_state", "kh3d_state", "constant_state",
     "random_smooth_state", "sine_state_scalar", "cell_centres", "mlmc_inputs",
-    "kh2d_state_and_jacobian",
+    "kh2d_state_and_jacobian", "primitive_polynomials", "sobol_points",
+    "kh_coefficients_qmc",
 ]
 
 
@@ -65,6 +72,108 @@ def kh3d_coefficients(seed: int, samples, modes: int = 10):
     m = modes
     return (u[:, :m].copy(), (2.0 * np.pi) * u[:, m:2 * m],
             u[:, 2 * m:3 * m].copy(), (2.0 * np.pi) * u[:, 3 * m:4 * m])
+
+
+def _gf2_mulmod(a: int, b: int, p: int, deg: int) -> int:
+    """a * b modulo the polynomial p of degree deg, polynomials over GF(2) as bit masks."""
+    r = 0
+    while b:
+        if b & 1:
+            r ^= a
+        b >>= 1
+        a <<= 1
+        if a >> deg & 1:
+            a ^= p
+    return r
+
+
+def _gf2_powmod(a: int, e: int, p: int, deg: int) -> int:
+    r = 1
+    while e:
+        if e & 1:
+            r = _gf2_mulmod(r, a, p, deg)
+        a = _gf2_mulmod(a, a, p, deg)
+        e >>= 1
+    return r
+
+
+def _prime_factors(n: int):
+    out, f = [], 2
+    while f * f <= n:
+        if n % f == 0:
+            out.append(f)
+            while n % f == 0:
+                n //= f
+        f += 1
+    if n > 1:
+        out.append(n)
+    return out
+
+
+def primitive_polynomials(count: int):
+    """The first `count` primitive polynomials over GF(2), by degree then value, as bit masks
+    (bit k the coefficient of x^k): p is primitive iff x has multiplicative order 2^d - 1
+    modulo p."""
+    out, deg = [], 1
+    while len(out) < count:
+        order = (1 << deg) - 1
+        for p in range((1 << deg) | 1, 1 << (deg + 1), 2):
+            x = 2 % p if deg > 1 else 1          # the residue of x (x = 1 modulo x + 1)
+            if _gf2_powmod(x, order, p, deg) != 1:
+                continue
+            if any(_gf2_powmod(x, order // r, p, deg) == 1 for r in _prime_factors(order) if r < order):
+                continue
+            out.append(p)
+            if len(out) == count:
+                break
+        deg += 1
+    return out
+
+
+SOBOL_BITS = 32
+
+
+def _sobol_directions(dim: int) -> np.ndarray:
+    """Direction numbers V[j][k] (k = 0..31 for bit k + 1) of the first `dim` coordinates."""
+    V = np.zeros((dim, SOBOL_BITS), dtype=np.uint64)
+    for k in range(SOBOL_BITS):
+        V[0, k] = 1 << (SOBOL_BITS - 1 - k)                   # van der Corput
+    polys = primitive_polynomials(max(dim - 1, 0))
+    for j in range(1, dim):
+        p = polys[j - 1]
+        s = p.bit_length() - 1                                 # degree
+        a = [(p >> (s - i)) & 1 for i in range(1, s)]          # a_1 .. a_{s-1}
+        m = [1] * s                                            # unit initial numbers
+        for k in range(s, SOBOL_BITS):
+            v = m[k - s] ^ (m[k - s] << s)
+            for i in range(1, s):
+                if a[i - 1]:
+                    v ^= m[k - i] << i
+            m.append(v)
+        for k in range(SOBOL_BITS):
+            V[j, k] = m[k] << (SOBOL_BITS - 1 - k)
+    return V
+
+
+def sobol_points(n: int, dim: int, skip: int = 0) -> np.ndarray:
+    """Points skip .. skip + n - 1 of the dim-dimensional Sobol sequence: float64 [n][dim] in
+    [0, 1), multiples of 2^-32."""
+    V = _sobol_directions(dim)
+    idx = np.arange(skip, skip + n, dtype=np.uint64)
+    X = np.zeros((n, dim), dtype=np.uint64)
+    for k in range(SOBOL_BITS):
+        bit = ((idx >> np.uint64(k)) & np.uint64(1)).astype(bool)
+        X[bit] ^= V[:, k]
+    return X.astype(np.float64) * 2.0 ** -SOBOL_BITS
+
+
+def kh_coefficients_qmc(samples, modes: int = 10, skip: int = 1):
+    """Quasi-Monte Carlo counterpart of kh_coefficients: sample s takes Sobol point
+    s + skip (point 0 is the origin) of dimension 2 * modes; c_k is coordinate k - 1 and
+    phi_k = 2 pi times coordinate modes + k - 1."""
+    samples = np.asarray(samples, dtype=np.int64)
+    pts = sobol_points(int(samples.max()) + 1, 2 * modes, skip=skip)[samples]
+    return pts[:, :modes].copy(), 2.0 * np.pi * pts[:, modes:]
 
 
 def cell_centres(n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:

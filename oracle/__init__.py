@@ -82,6 +82,14 @@ def lib():
         L.oc_stats_accumulate_diff.argtypes = [P, P, dp, dp, C.c_int64, dp, dp,
                                                C.POINTER(C.c_int64)]
         L.oc_mlmc_combine.argtypes = [C.c_int32, P, C.POINTER(dp), dp]
+        ip = C.POINTER(C.c_int64)
+        L.oc_point_pdf.argtypes = [P, dp, C.c_int64, C.c_int32, C.c_int64, ip, C.c_double,
+                                   C.c_double, C.c_int32, ip]
+        L.oc_joint_pdf.argtypes = [P, dp, C.c_int64, C.c_int32, C.c_int32, C.c_int64, ip,
+                                   C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, ip]
+        L.oc_structure_shell.argtypes = [P, dp, C.c_int64, C.c_int32, C.c_int32]
+        L.oc_structure_shell.restype = C.c_double
+        L.oc_structure_shell_batch.argtypes = [P, dp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, dp]
         _lib = L
     return _lib
 
@@ -233,6 +241,53 @@ def structure_function(p: Problem, q: np.ndarray, h: int) -> float:
     q = np.ascontiguousarray(q, dtype=np.float64)
     assert q.size == p.cells
     return lib().oc_structure_function(p.c, _dp(q), int(h))
+
+
+def _ip(a: np.ndarray):
+    assert a.dtype == np.int64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def point_pdf(p: Problem, U: np.ndarray, quantity: int, points, lo: float, hi: float,
+              nbins: int) -> np.ndarray:
+    """Histogram over the samples U[batch] of `quantity` at each cell of `points`:
+    int64 [npoints][nbins + 2] (bins, below lo, not below hi)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    pts = np.ascontiguousarray(points, dtype=np.int64)
+    counts = np.zeros((pts.size, nbins + 2), dtype=np.int64)
+    _check(lib().oc_point_pdf(p.c, _dp(U), U.shape[0], int(quantity), pts.size, _ip(pts),
+                              float(lo), float(hi), int(nbins), _ip(counts)), "oc_point_pdf")
+    return counts
+
+
+def joint_pdf(p: Problem, U: np.ndarray, quantity_a: int, quantity_b: int, pairs, lo_a: float,
+              hi_a: float, lo_b: float, hi_b: float, nbins: int) -> np.ndarray:
+    """Histogram over samples of (q_a(x), q_b(y)) for each pair (x, y) of cells:
+    int64 [npairs][nbins * nbins + 1] (bin ka * nbins + kb, then outside)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    counts = np.zeros((pr.shape[0], nbins * nbins + 1), dtype=np.int64)
+    _check(lib().oc_joint_pdf(p.c, _dp(U), U.shape[0], int(quantity_a), int(quantity_b),
+                              pr.shape[0], _ip(pr), float(lo_a), float(hi_a), float(lo_b),
+                              float(hi_b), int(nbins), _ip(counts)), "oc_joint_pdf")
+    return counts
+
+
+def structure_shell(p: Problem, q: np.ndarray, h: int, order: int = 2, ball: bool = False) -> float:
+    """S_order(h) of one periodic field q over the cube (or ball) shell of radius h."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    assert q.size == p.cells
+    return lib().oc_structure_shell(p.c, _dp(q), int(h), int(order), int(bool(ball)))
+
+
+def structure_shell_batch(p: Problem, U: np.ndarray, max_h: int, order: int = 2,
+                          ball: bool = False) -> np.ndarray:
+    """Shell structure functions of every quantity of every sample: [batch][quantities][max_h]."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.zeros((U.shape[0], p.nfields, max_h), dtype=np.float64)
+    _check(lib().oc_structure_shell_batch(p.c, _dp(U), U.shape[0], int(max_h), int(order),
+                                          int(bool(ball)), _dp(out)), "oc_structure_shell_batch")
+    return out
 
 
 class LevelStats:

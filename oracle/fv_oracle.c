@@ -15,8 +15,9 @@
  *     reconstructions (piecewise constant, MUSCL with minmod, third-order WENO) and the SSP
  *     Runge--Kutta time steppers (forward Euler, SSP-RK2, SSP-RK3) named in Section 2.1;
  *   - a CFL time step from the maximum wave speed, and the Monte Carlo statistics named in
- *     Section 2.2 (per-cell mean and variance over samples, two-point structure functions),
- *     and the single- and multi-level Monte Carlo estimators of Section 2.2.
+ *     Section 2.2 (per-cell mean and variance over samples, two-point structure functions
+ *     along the axes and over cube or ball shells, point and joint PDFs), and the single-
+ *     and multi-level Monte Carlo estimators of Section 2.2.
  *
  * Every pass is a separate loop over plain arrays in the order the method takes it:
  * ghost fill into a padded copy, reconstruction of the two face values of every cell,
@@ -655,6 +656,166 @@ int oc_stats_accumulate(const oc_problem* P, const double* U, int64_t batch, int
                 welford(s, n, &s2mean[qi * max_h + (h - 1)], &s2m2[qi * max_h + (h - 1)]);
             }
         *count = n;
+    }
+    free(q);
+    return OC_OK;
+}
+
+/* ---------------------------------------------------------------- PDFs, shell structure functions
+ *
+ * Section 2.2 lists point PDFs, joint PDFs and two-point structure functions among the
+ * statistics (after Fjordholm, Lye and Mishra) and prints no formula for them. Readings:
+ *   - point PDF: the histogram over samples of one quantity at one cell. nbins equal bins
+ *     on [lo, hi): bin k = floor(((v - lo) / (hi - lo)) * nbins), taken as nbins - 1 if
+ *     rounding gives nbins; one more counter for values below lo and one for values not
+ *     below hi (NaN included), so the counters of a point add up to the number of samples;
+ *   - joint PDF: the histogram over samples of the pair (quantity a at cell x, quantity b at
+ *     cell y) on nbins x nbins such bins, plus one counter for pairs with either value
+ *     outside its range;
+ *   - shell structure function of order p in {1, 2} at radius h on the periodic grid:
+ *     S_p(h) = 1/(N |A_h|) sum_{o in A_h} sum_x |q(x + o) - q(x)|^p, where A_h is the cube
+ *     shell {o in Z^d : max_k |o_k| = h} or the ball shell {o : (h-1)^2 < |o|^2 <= h^2}.
+ *     Offsets are taken with o_z, o_y, o_x ascending, cells in row-major order.
+ */
+
+/* Bin of v: 0..nbins-1, -1 below lo, nbins not below hi. */
+static int pdf_bin(double v, double lo, double hi, int32_t nbins)
+{
+    if (v < lo) return -1;
+    if (!(v < hi)) return nbins;
+    const int64_t k = (int64_t)floor(((v - lo) / (hi - lo)) * (double)nbins);
+    return (int)(k < nbins ? k : nbins - 1);
+}
+
+/* Quantity qi of one sample U[fields][cells] at cell c (as oc_quantities computes it). */
+static double cell_quantity(const oc_problem* P, const double* U, int64_t c, int qi)
+{
+    const int64_t N = cells_of(P);
+    if (P->eq != OC_EQ_EULER || qi == 0 || qi == oc_num_fields(P) - 1) return U[qi * N + c];
+    double ir = 1.0 / U[c];
+    return U[qi * N + c] * ir;
+}
+
+static int pdf_args_ok(const oc_problem* P, int32_t quantity, double lo, double hi, int32_t nbins)
+{
+    return quantity >= 0 && quantity < oc_num_quantities(P) && nbins >= 1 && lo < hi;
+}
+
+/* Point PDFs of quantity at cells points[npoints] over the samples U[batch], added to
+ * counts[npoints][nbins + 2] (bins, then below, then above). */
+int oc_point_pdf(const oc_problem* P, const double* U, int64_t batch, int32_t quantity,
+                 int64_t npoints, const int64_t* points, double lo, double hi, int32_t nbins,
+                 int64_t* counts)
+{
+    int st = oc_validate(P);
+    if (st) return st;
+    const int64_t N = cells_of(P);
+    if (!pdf_args_ok(P, quantity, lo, hi, nbins) || batch < 0 || npoints < 0) return OC_EINVAL;
+    for (int64_t i = 0; i < npoints; ++i)
+        if (points[i] < 0 || points[i] >= N) return OC_EINVAL;
+    const int nf = oc_num_fields(P);
+    for (int64_t b = 0; b < batch; ++b)
+        for (int64_t i = 0; i < npoints; ++i) {
+            const int k = pdf_bin(cell_quantity(P, U + b * nf * N, points[i], quantity), lo, hi, nbins);
+            const int slot = (k < 0) ? nbins : (k >= nbins ? nbins + 1 : k);
+            counts[i * (nbins + 2) + slot] += 1;
+        }
+    return OC_OK;
+}
+
+/* Joint PDFs of (quantity_a at pairs[i][0], quantity_b at pairs[i][1]) over the samples,
+ * added to counts[npairs][nbins * nbins + 1] (bin ka * nbins + kb, then outside). */
+int oc_joint_pdf(const oc_problem* P, const double* U, int64_t batch, int32_t quantity_a,
+                 int32_t quantity_b, int64_t npairs, const int64_t* pairs, double lo_a,
+                 double hi_a, double lo_b, double hi_b, int32_t nbins, int64_t* counts)
+{
+    int st = oc_validate(P);
+    if (st) return st;
+    const int64_t N = cells_of(P);
+    if (!pdf_args_ok(P, quantity_a, lo_a, hi_a, nbins) || !pdf_args_ok(P, quantity_b, lo_b, hi_b, nbins) ||
+        batch < 0 || npairs < 0)
+        return OC_EINVAL;
+    for (int64_t i = 0; i < 2 * npairs; ++i)
+        if (pairs[i] < 0 || pairs[i] >= N) return OC_EINVAL;
+    const int nf = oc_num_fields(P);
+    const int64_t per = (int64_t)nbins * nbins + 1;
+    for (int64_t b = 0; b < batch; ++b)
+        for (int64_t i = 0; i < npairs; ++i) {
+            const double* Ub = U + b * nf * N;
+            const int ka = pdf_bin(cell_quantity(P, Ub, pairs[2 * i], quantity_a), lo_a, hi_a, nbins);
+            const int kb = pdf_bin(cell_quantity(P, Ub, pairs[2 * i + 1], quantity_b), lo_b, hi_b, nbins);
+            const int64_t slot = (ka < 0 || ka >= nbins || kb < 0 || kb >= nbins)
+                                     ? per - 1 : (int64_t)ka * nbins + kb;
+            counts[i * per + slot] += 1;
+        }
+    return OC_OK;
+}
+
+static int64_t wrap64(int64_t i, int64_t n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+/* Is o in the shell A_h (cube or ball)? */
+static int in_shell(int64_t ox, int64_t oy, int64_t oz, int64_t h, int ball)
+{
+    if (ball) {
+        const int64_t r2 = ox * ox + oy * oy + oz * oz;
+        return (h - 1) * (h - 1) < r2 && r2 <= h * h;
+    }
+    int64_t m = ox < 0 ? -ox : ox;
+    const int64_t ay = oy < 0 ? -oy : oy, az = oz < 0 ? -oz : oz;
+    if (ay > m) m = ay;
+    if (az > m) m = az;
+    return m == h;
+}
+
+/* S_p(h) of one periodic field q[cells] over the cube (ball = 0) or ball (ball = 1) shell. */
+double oc_structure_shell(const oc_problem* P, const double* q, int64_t h, int32_t p, int32_t ball)
+{
+    const int64_t nx = P->n[0], ny = P->n[1], nz = P->n[2];
+    const int64_t hy = (P->dim >= 2) ? h : 0, hz = (P->dim >= 3) ? h : 0;
+    double s = 0.0;
+    int64_t shell = 0;
+    for (int64_t oz = -hz; oz <= hz; ++oz)
+        for (int64_t oy = -hy; oy <= hy; ++oy)
+            for (int64_t ox = -h; ox <= h; ++ox) {
+                if (!in_shell(ox, oy, oz, h, ball)) continue;
+                shell += 1;
+                for (int64_t k = 0; k < nz; ++k)
+                    for (int64_t j = 0; j < ny; ++j)
+                        for (int64_t i = 0; i < nx; ++i) {
+                            const int64_t c2 = (wrap64(k + oz, nz) * ny + wrap64(j + oy, ny)) * nx + wrap64(i + ox, nx);
+                            const double d = q[c2] - q[(k * ny + j) * nx + i];
+                            s = s + ((p == 1) ? fabs(d) : (d * d));
+                        }
+            }
+    return s / ((double)cells_of(P) * (double)shell);
+}
+
+/* Shell structure functions of every quantity of every sample: out[batch][quantities][max_h]
+ * with out[b][q][h - 1] = S_p(h) of quantity q of sample b. Periodic grids only, with
+ * max_h < n on every active axis (OC_ENOTSUP otherwise). */
+int oc_structure_shell_batch(const oc_problem* P, const double* U, int64_t batch, int32_t max_h,
+                             int32_t p, int32_t ball, double* out)
+{
+    int st = oc_validate(P);
+    if (st) return st;
+    if (max_h < 1 || (p != 1 && p != 2) || (ball != 0 && ball != 1) || batch < 0) return OC_EINVAL;
+    for (int k = 0; k < P->dim; ++k)
+        if (P->bc[k] != OC_BC_PERIODIC || max_h >= P->n[k]) return OC_ENOTSUP;
+    const int nf = oc_num_fields(P);
+    const int nq = oc_num_quantities(P);
+    const int64_t N = cells_of(P);
+    double* q = (double*)malloc(sizeof(double) * (size_t)(N * nq));
+    if (!q) return OC_ENOMEM;
+    for (int64_t b = 0; b < batch; ++b) {
+        oc_quantities(P, U + b * N * nf, q);
+        #pragma omp parallel for schedule(dynamic) collapse(2)
+        for (int qi = 0; qi < nq; ++qi)
+            for (int32_t h = 1; h <= max_h; ++h)
+                out[(b * nq + qi) * max_h + (h - 1)] = oc_structure_shell(P, q + qi * N, h, p, ball);
     }
     free(q);
     return OC_OK;
