@@ -222,6 +222,47 @@ fv_status fv_stats_reset(fv_stats* stats);
 
 fv_status fv_stats_destroy(fv_stats* stats);
 
+/* ------------------------------------------------------------------ PDFs and shell structure functions */
+
+/* Point PDFs (Section 2.2 lists them among the statistics, after Fjordholm, Lye and Mishra):
+ * for every cell points[i] (host int64 array of npoints cell indices, x fastest), the
+ * histogram over the batch's samples of one quantity (as for fv_stats_create: Euler rho,
+ * u_1..u_dim, E with u_k = m_k * (1/rho); scalar equations the field, quantity 0) at that
+ * cell. nbins equal bins on [lo, hi): a value v in range goes to bin
+ * floor(((v - lo) / (hi - lo)) * nbins) computed in FP64 in that order, or to the last bin
+ * if that rounds to nbins. counts: device int64 [npoints][nbins + 2], ADDED to (the caller
+ * clears it): the bins, then one counter for values below lo and one for values not below hi
+ * (NaN included). Exact integer counts, independent of launch order. state: device
+ * double[batch][fields][cells]. FV_EINVAL: a NULL pointer, batch < 1, npoints < 0, no such
+ * quantity, nbins outside 1..65536, !(lo < hi), a cell index outside the grid. Stream-ordered;
+ * `points` may be reused when the call returns. */
+fv_status fv_point_pdf(const fv_solver* solver, const double* state, int64_t batch,
+                       int32_t quantity, int64_t npoints, const int64_t* points, double lo,
+                       double hi, int32_t nbins, int64_t* counts);
+
+/* Joint PDFs: for every pair (pairs[i][0], pairs[i][1]) of cells (host int64 [npairs][2]),
+ * the histogram over samples of (quantity_a at the first cell, quantity_b at the second) on
+ * nbins x nbins bins of [lo_a, hi_a) x [lo_b, hi_b), each axis binned as in fv_point_pdf.
+ * counts: device int64 [npairs][nbins * nbins + 1], ADDED to: bin ka * nbins + kb, then one
+ * counter for pairs with either value outside its range. Errors as for fv_point_pdf. */
+fv_status fv_joint_pdf(const fv_solver* solver, const double* state, int64_t batch,
+                       int32_t quantity_a, int32_t quantity_b, int64_t npairs,
+                       const int64_t* pairs, double lo_a, double hi_a, double lo_b,
+                       double hi_b, int32_t nbins, int64_t* counts);
+
+/* Structure functions over cube or ball shells (the two-point structure functions of
+ * Section 2.2 in the averaged form of Fjordholm, Lye and Mishra), per sample:
+ * out[b][q][h - 1] = S_p(h) = 1/(N |A_h|) sum_{o in A_h} sum_x |q(x + o) - q(x)|^p for
+ * h = 1..max_h on the periodic grid, p = order in {1, 2}, with the cube shell
+ * A_h = {o : max_k |o_k| = h} (ball = 0) or the ball shell {o : (h-1)^2 < |o|^2 <= h^2}
+ * (ball = 1), o over the grid's axes. out: device double [batch][quantities][max_h].
+ * Sums are taken per cell over the shell, then over cells; they agree with the definition's
+ * order to rounding. FV_EINVAL: a NULL pointer, batch < 1, max_h outside 1..64, order or ball
+ * out of range. FV_ENOTSUP: a non-periodic axis, max_h >= cells of an axis, or a tile with its
+ * halo beyond 64 KB of LDS (3D: max_h <= 6; 2D: max_h <= 36). Stream-ordered. */
+fv_status fv_structure_shell(const fv_solver* solver, const double* state, int64_t batch,
+                             int32_t max_h, int32_t order, int32_t ball, double* out);
+
 /* ------------------------------------------------------------------ discrete adjoint */
 
 /* Discrete adjoint of a fixed-step run (not in the paper; it differentiates the scheme of

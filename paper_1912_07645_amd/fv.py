@@ -69,6 +69,10 @@ def _load():
         "fv_mlmc_combine": (i32, [i32, C.POINTER(vp), vp]),
         "fv_stats_destroy": (i32, [vp]),
         "fv_check_arith": (i32, [vp, vp, vp, vp, i64]),
+        "fv_point_pdf": (i32, [vp, vp, i64, i32, i64, C.POINTER(i64), dbl, dbl, i32, vp]),
+        "fv_joint_pdf": (i32, [vp, vp, i64, i32, i32, i64, C.POINTER(i64), dbl, dbl, dbl, dbl,
+                               i32, vp]),
+        "fv_structure_shell": (i32, [vp, vp, i64, i32, i32, i32, vp]),
         "fv_adjoint_create": (i32, [vp, i64, i64, dbl, i64, dbl, C.POINTER(vp)]),
         "fv_adjoint_forward": (i32, [vp, vp, vp]),
         "fv_adjoint_backward": (i32, [vp, vp, vp]),
@@ -255,6 +259,30 @@ def fv_stats_reset(stats) -> None:
 
 def fv_stats_destroy(stats) -> None:
     check(lib.fv_stats_destroy(stats), "fv_stats_destroy")
+
+
+def _host_i64(cells):
+    arr = (C.c_int64 * len(cells))(*[int(c) for c in cells])
+    return arr
+
+
+def fv_point_pdf(solver, state, batch, quantity, points, lo, hi, nbins, counts) -> None:
+    pts = [int(p) for p in points]
+    check(lib.fv_point_pdf(solver, ptr(state), int(batch), int(quantity), len(pts), _host_i64(pts),
+                           float(lo), float(hi), int(nbins), ptr(counts)), "fv_point_pdf")
+
+
+def fv_joint_pdf(solver, state, batch, quantity_a, quantity_b, pairs, lo_a, hi_a, lo_b, hi_b,
+                 nbins, counts) -> None:
+    flat = [int(c) for pr in pairs for c in pr]
+    check(lib.fv_joint_pdf(solver, ptr(state), int(batch), int(quantity_a), int(quantity_b),
+                           len(flat) // 2, _host_i64(flat), float(lo_a), float(hi_a), float(lo_b),
+                           float(hi_b), int(nbins), ptr(counts)), "fv_joint_pdf")
+
+
+def fv_structure_shell(solver, state, batch, max_h, order, ball, out) -> None:
+    check(lib.fv_structure_shell(solver, ptr(state), int(batch), int(max_h), int(order),
+                                 int(bool(ball)), ptr(out)), "fv_structure_shell")
 
 
 def fv_check_arith(a, b, quot, root) -> None:

@@ -86,6 +86,41 @@ class Solver:
         self._prepare(B)
         return fv.fv_evolve_fixed_dt(self.handle, U, B, dt, nsteps, cfl_bound, err)
 
+    @property
+    def num_quantities(self) -> int:
+        return self.nf if self.names["eq"] == "euler" else 1
+
+    def point_pdf(self, U, quantity, points, lo, hi, nbins, counts=None):
+        """Histograms over the samples of U of `quantity` at each cell of `points` (flat cell
+        indices): int64 [len(points)][nbins + 2] (bins, below lo, not below hi), added to
+        `counts` if given."""
+        B = self._check_state(U)
+        if counts is None:
+            counts = torch.zeros((len(points), nbins + 2), dtype=torch.int64, device=self.device)
+        fv.fv_set_stream(self.handle, torch.cuda.current_stream(self.device).cuda_stream)
+        fv.fv_point_pdf(self.handle, U, B, quantity, points, lo, hi, nbins, counts)
+        return counts
+
+    def joint_pdf(self, U, quantity_a, quantity_b, pairs, lo_a, hi_a, lo_b, hi_b, nbins, counts=None):
+        """Histograms over samples of (quantity_a at x, quantity_b at y) for each pair (x, y):
+        int64 [len(pairs)][nbins * nbins + 1] (bins, then outside), added to `counts` if given."""
+        B = self._check_state(U)
+        if counts is None:
+            counts = torch.zeros((len(pairs), nbins * nbins + 1), dtype=torch.int64, device=self.device)
+        fv.fv_set_stream(self.handle, torch.cuda.current_stream(self.device).cuda_stream)
+        fv.fv_joint_pdf(self.handle, U, B, quantity_a, quantity_b, pairs, lo_a, hi_a, lo_b, hi_b,
+                        nbins, counts)
+        return counts
+
+    def structure_shell(self, U, max_h, order=2, ball=False):
+        """Per-sample structure functions over cube (or ball) shells:
+        float64 [batch][quantities][max_h], entry h - 1 for radius h."""
+        B = self._check_state(U)
+        out = torch.empty((B, self.num_quantities, max_h), dtype=torch.float64, device=self.device)
+        fv.fv_set_stream(self.handle, torch.cuda.current_stream(self.device).cuda_stream)
+        fv.fv_structure_shell(self.handle, U, B, max_h, order, ball, out)
+        return out
+
     def num_variants(self) -> int:
         return fv.fv_num_variants(self.handle)
 

@@ -81,3 +81,12 @@ def test_product_path_has_no_cpu_fallback():
         if f.endswith((".py", ".c")):
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_1912_07645_amd" not in text, f
+
+
+def test_functionals_reject_null_arguments_without_device():
+    import paper_1912_07645_amd.fv as fv
+    L = fv.lib
+    pts = (C.c_int64 * 1)(0)
+    assert L.fv_point_pdf(None, None, 1, 0, 1, pts, 0.0, 1.0, 4, None) == fv.FV_EINVAL
+    assert L.fv_joint_pdf(None, None, 1, 0, 0, 1, pts, 0.0, 1.0, 0.0, 1.0, 4, None) == fv.FV_EINVAL
+    assert L.fv_structure_shell(None, None, 1, 2, 2, 0, None) == fv.FV_EINVAL
