@@ -280,6 +280,43 @@ def run_adjoint(a, w):
     return out
 
 
+# LDS roof of the shell structure functions: every (cell, offset) term reads one double from
+# LDS (plus 3 FP64 operations, whose issue ceiling, 13.1e12 terms/s, lies above): 256 CUs x
+# 128 B per clock x 2.4 GHz / 8 B.
+SHELL_TERMS_PEAK = 256 * 128 * 2.4e9 / 8
+
+
+def functionals(s, U, cells, B):
+    """Point PDFs (1024 cells x 4 quantities, 64 bins), joint PDFs (256 pairs of neighbouring
+    cells, 32 x 32 bins) and cube-shell structure functions (order 2, radius 1..8) of the
+    batch, each timed once after an untimed call."""
+    import torch
+    N = cells
+    points = list(range(0, N, max(1, N // 1024)))[:1024]
+    pairs = [(c, (c + 1) % N) for c in points[:256]]
+    ranges = ((0.9, 2.1), (-0.6, 0.6), (-0.05, 0.05), (2.4, 3.6))
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3
+
+    out["point_pdf_ms"] = timed(lambda: [s.point_pdf(U, q, points, lo, hi, 64)
+                                         for q, (lo, hi) in enumerate(ranges)])
+    out["joint_pdf_ms"] = timed(lambda: s.joint_pdf(U, 0, 3, pairs, *ranges[0], *ranges[3], 32))
+    H = 8
+    ms = timed(lambda: s.structure_shell(U, H, 2, False))
+    terms = N * B * s.num_quantities * sum(8 * h for h in range(1, H + 1))   # 2D cube shells
+    out["shell_cube_h8_ms"] = ms
+    out["shell_terms_per_s"] = terms / (ms * 1e-3)
+    out["shell_lds_roof_frac"] = terms / (ms * 1e-3) / SHELL_TERMS_PEAK
+    return out
+
+
 def per_sample_rate(s, U, cfl, K, B1):
     """The same kernels with one sample per launch (the unbatched way), over B1 samples."""
     import torch
@@ -440,7 +477,7 @@ def measure(a, w, steps=None, warmup=None):
         mc = measure(ea, dict(WORKLOADS["mc"]), steps=20, warmup=2)
         out["batched_mc"] = {k: mc[k] for k in (
             "mc_sample_steps_per_s", "per_sample_launch_sample_steps_per_s",
-            "batched_speedup_over_per_sample_launches", "stats_ms_for_batch")}
+            "batched_speedup_over_per_sample_launches", "stats_ms_for_batch", "functionals")}
         out["batched_mc"]["config"] = mc["config"]["workload"]
         adj = run_adjoint(argparse.Namespace(steps=1, warmup=1, variant=None), WORKLOADS["adjoint"])
         out["adjoint"] = {k: adj[k] for k in ("forward_ms", "gradient_ms",
@@ -465,6 +502,7 @@ def measure(a, w, steps=None, warmup=None):
         res = st.read()
         torch.cuda.synchronize()
         out["stats_ms_for_batch"] = (time.perf_counter() - t0) * 1e3
+        out["functionals"] = functionals(s, U, cells, B)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, U0, w["cpu_steps"])
     return out
