@@ -23,8 +23,8 @@ _BUILD = os.path.join(_HERE, "_build")
 _SO = os.path.join(_BUILD, "liboracle.so")
 
 EQ = {"advection": 0, "burgers": 1, "euler": 2}
-FLUX = {"rusanov": 0, "hll": 1, "hllc": 2}
-RECON = {"first_order": 0, "muscl_minmod": 1, "weno3": 2}
+FLUX = {"rusanov": 0, "hll": 1, "hllc": 2, "roe": 3, "ec": 4}
+RECON = {"first_order": 0, "muscl_minmod": 1, "weno3": 2, "eno2": 3}
 INTEGRATOR = {"forward_euler": 0, "ssprk2": 1, "ssprk3": 2}
 BC = {"periodic": 0, "transmissive": 1}
 STATUS = {0: "ok", 1: "einval", 2: "enotsup", 3: "enomem", 5: "enonphys", 6: "emaxsteps",
@@ -82,6 +82,7 @@ def lib():
         L.oc_stats_accumulate_diff.argtypes = [P, P, dp, dp, C.c_int64, dp, dp,
                                                C.POINTER(C.c_int64)]
         L.oc_mlmc_combine.argtypes = [C.c_int32, P, C.POINTER(dp), dp]
+        L.oc_reconstruct.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp, dp]
         ip = C.POINTER(C.c_int64)
         L.oc_point_pdf.argtypes = [P, dp, C.c_int64, C.c_int32, C.c_int64, ip, C.c_double,
                                    C.c_double, C.c_int32, ip]
@@ -228,6 +229,13 @@ def numerical_flux(p: Problem, nd: int, UL, UR) -> np.ndarray:
 
 def weno3(a: float, b: float, c: float) -> float:
     return lib().oc_weno3(float(a), float(b), float(c))
+
+
+def reconstruct(recon: str, um: float, u0: float, up: float):
+    """Face values (at i - 1/2, at i + 1/2) of the cell u0 between um and up."""
+    lo, hi = C.c_double(), C.c_double()
+    lib().oc_reconstruct(RECON[recon], float(um), float(u0), float(up), C.byref(lo), C.byref(hi))
+    return lo.value, hi.value
 
 
 def quantities(p: Problem, U: np.ndarray) -> np.ndarray:

@@ -40,7 +40,14 @@
  *     U^(s) = U^n + beta_s ((U^(s-1) - U^n) + dt L(U^(s-1))), beta = {1}, {1, 1/2},
  *     {1, 1/4, 2/3}, algebraically the Shu--Osher form;
  *   - dt = cfl / max_cells max_d (|u_d| + c) / dx_d, the last step clipped to end at T;
- *   - transmissive boundaries copy the edge cell into every ghost layer.
+ *   - transmissive boundaries copy the edge cell into every ghost layer;
+ *   - the Roe flux (Section 2.1 names it) uses Roe's average state and Harten's entropy fix
+ *     on the acoustic waves (roe_euler); for Burgers the Roe speed is (uL + uR) / 2 with the
+ *     fix over the rarefaction fan, for advection the velocity (plain upwinding);
+ *   - the high-order entropy-conservative fluxes Section 2.1 names are taken, for Burgers, as
+ *     Tadmor's two-point flux (uL^2 + uL uR + uR^2) / 6;
+ *   - ENO (Section 2.1) is the second-order ENO reconstruction: the one-sided difference of
+ *     smaller magnitude, the left one on a tie.
  */
 #include <math.h>
 #include <stdint.h>
@@ -54,8 +61,8 @@
 /* ---------------------------------------------------------------- problem description */
 
 enum { OC_EQ_ADVECTION = 0, OC_EQ_BURGERS = 1, OC_EQ_EULER = 2 };
-enum { OC_FLUX_RUSANOV = 0, OC_FLUX_HLL = 1, OC_FLUX_HLLC = 2 };
-enum { OC_REC_FIRST = 0, OC_REC_MUSCL = 1, OC_REC_WENO3 = 2 };
+enum { OC_FLUX_RUSANOV = 0, OC_FLUX_HLL = 1, OC_FLUX_HLLC = 2, OC_FLUX_ROE = 3, OC_FLUX_EC = 4 };
+enum { OC_REC_FIRST = 0, OC_REC_MUSCL = 1, OC_REC_WENO3 = 2, OC_REC_ENO2 = 3 };
 enum { OC_INT_FE = 0, OC_INT_RK2 = 1, OC_INT_RK3 = 2 };
 enum { OC_BC_PERIODIC = 0, OC_BC_TRANSMISSIVE = 1 };
 enum { OC_OK = 0, OC_EINVAL = 1, OC_ENOTSUP = 2, OC_ENOMEM = 3,
@@ -87,7 +94,7 @@ static int64_t cells_of(const oc_problem* P)
     return P->n[0] * P->n[1] * P->n[2];
 }
 
-/* Two ghost layers on every active axis: the widest stencil (MUSCL, WENO3) reaches two
+/* Two ghost layers on every active axis: the widest stencil (MUSCL, ENO2, WENO3) reaches two
  * cells beyond a face; piecewise-constant reconstruction uses only the first layer. */
 static int ghost_width(const oc_problem* P)
 {
@@ -105,10 +112,11 @@ int oc_validate(const oc_problem* P)
         if (P->bc[k] != OC_BC_PERIODIC && P->bc[k] != OC_BC_TRANSMISSIVE) return OC_EINVAL;
     }
     if (P->eq < 0 || P->eq > 2) return OC_EINVAL;
-    if (P->flux < 0 || P->flux > 2) return OC_EINVAL;
-    if (P->recon < 0 || P->recon > 2) return OC_EINVAL;
+    if (P->flux < 0 || P->flux > 4) return OC_EINVAL;
+    if (P->recon < 0 || P->recon > 3) return OC_EINVAL;
     if (P->integrator < 0 || P->integrator > 2) return OC_EINVAL;
     if (P->flux == OC_FLUX_HLLC && P->eq != OC_EQ_EULER) return OC_ENOTSUP;
+    if (P->flux == OC_FLUX_EC && P->eq != OC_EQ_BURGERS) return OC_ENOTSUP;
     if (P->eq == OC_EQ_EULER && !(P->gamma > 1.0)) return OC_EINVAL;
     return OC_OK;
 }
@@ -161,6 +169,68 @@ static void euler_flux(const double* U, const oc_prim* w, int dim, int nd, doubl
 
 /* ---------------------------------------------------------------- numerical fluxes */
 
+/* Harten's entropy fix of a wave speed l with fan width d >= 0: |l| where |l| >= d, else
+ * (l^2 + d^2) / (2 d). */
+static double harten(double l, double d)
+{
+    const double al = fabs(l);
+    return (al >= d) ? al : (((l * l) + (d * d)) / (2.0 * d));
+}
+
+/* Roe's flux for the Euler equations: F = (F_L + F_R)/2 - (1/2) sum_i |l_i| alpha_i K_i over
+ * the eigen-decomposition of the Jacobian at Roe's average state (u~, H~ weighted by sqrt(rho);
+ * a~^2 = (gamma - 1)(H~ - |u~|^2 / 2); rho~ = sqrt(rho_L rho_R)), with the wave strengths
+ *   alpha_1 = (dp - rho~ a~ du_n) / (2 a~^2),  alpha_2 = d rho - dp / a~^2,
+ *   alpha_3 = (dp + rho~ a~ du_n) / (2 a~^2),  beta_k = rho~ du_k (k tangential),
+ * the eigenvectors K_1 = (1, u~ - a~ n, H~ - u~_n a~), K_2 = (1, u~, |u~|^2/2),
+ * K_3 = (1, u~ + a~ n, H~ + u~_n a~) and the shear vectors (0, e_k, u~_k), and Harten's fix
+ * on the acoustic speeds with fan widths d_1,3 = max(0, l_1,3(U_R) - l_1,3(U_L)) / 2. The
+ * waves are summed in the order 1, 2, shear (k ascending), 3. */
+static void roe_euler(const double* UL, const double* UR, const oc_prim* wl, const oc_prim* wr,
+                      const double* FL, const double* FR, int dim, int nd, double gm1, double* Fh)
+{
+    const double sL = sqrt(UL[0]), sR = sqrt(UR[0]);
+    const double ssum = sL + sR;
+    const double HL = (UL[dim + 1] + wl->p) * wl->ir;
+    const double HR = (UR[dim + 1] + wr->p) * wr->ir;
+    double ut[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k) ut[k] = ((sL * wl->u[k]) + (sR * wr->u[k])) / ssum;
+    const double Ht = ((sL * HL) + (sR * HR)) / ssum;
+    double q2 = ut[0] * ut[0];
+    for (int k = 1; k < dim; ++k) q2 = q2 + (ut[k] * ut[k]);
+    const double a2 = gm1 * (Ht - (0.5 * q2));
+    const double a = sqrt(a2);
+    const double rt = sL * sR;
+    const double un = ut[nd];
+    const double dr = UR[0] - UL[0];
+    const double dp = wr->p - wl->p;
+    const double dun = wr->u[nd] - wl->u[nd];
+    const double ra = rt * a;
+    const double alpha1 = (dp - (ra * dun)) / (2.0 * a2);
+    const double alpha2 = dr - (dp / a2);
+    const double alpha3 = (dp + (ra * dun)) / (2.0 * a2);
+    const double d1 = 0.5 * dmax(0.0, (wr->u[nd] - wr->c) - (wl->u[nd] - wl->c));
+    const double d3 = 0.5 * dmax(0.0, (wr->u[nd] + wr->c) - (wl->u[nd] + wl->c));
+    const double w1 = harten(un - a, d1) * alpha1;
+    const double w2 = fabs(un) * alpha2;
+    const double w3 = harten(un + a, d3) * alpha3;
+    double ws[3] = {0.0, 0.0, 0.0};   /* shear waves */
+    for (int k = 0; k < dim; ++k)
+        if (k != nd) ws[k] = fabs(un) * (rt * (wr->u[k] - wl->u[k]));
+    double D[OC_MAXF];
+    D[0] = (w1 + w2) + w3;
+    for (int k = 0; k < dim; ++k) {
+        double t = (w1 * ((k == nd) ? (ut[k] - a) : ut[k])) + (w2 * ut[k]);
+        if (k != nd) t = t + ws[k];
+        D[1 + k] = t + (w3 * ((k == nd) ? (ut[k] + a) : ut[k]));
+    }
+    double e = (w1 * (Ht - (un * a))) + (w2 * (0.5 * q2));
+    for (int k = 0; k < dim; ++k)
+        if (k != nd) e = e + (ws[k] * ut[k]);
+    D[dim + 1] = e + (w3 * (Ht + (un * a)));
+    for (int q = 0; q < dim + 2; ++q) Fh[q] = 0.5 * ((FL[q] + FR[q]) - D[q]);
+}
+
 /* Numerical flux across a face with normal direction nd, from the reconstructed states
  * UL (left of the face) and UR (right of the face). */
 void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const double* UR,
@@ -181,6 +251,10 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
             double s = dmax(fabs(uL) + wl.c, fabs(uR) + wr.c);
             for (int q = 0; q < nf; ++q)
                 Fh[q] = 0.5 * ((FL[q] + FR[q]) - (s * (UR[q] - UL[q])));
+            return;
+        }
+        if (P->flux == OC_FLUX_ROE) {
+            roe_euler(UL, UR, &wl, &wr, FL, FR, dim, nd, gm1, Fh);
             return;
         }
         double SL = dmin(uL - wl.c, uR - wr.c);
@@ -234,6 +308,25 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
         Fh[0] = 0.5 * ((FL + FR) - (s * (uR - uL)));
         return;
     }
+    if (P->flux == OC_FLUX_ROE) {
+        /* Roe speed: the mean for Burgers (the exact Rankine--Hugoniot speed), the velocity for
+         * advection; Harten's fix over the fan width of a Burgers rarefaction */
+        double a, d;
+        if (P->eq == OC_EQ_BURGERS) {
+            a = 0.5 * (uL + uR);
+            d = 0.5 * dmax(0.0, uR - uL);
+        } else {
+            a = P->vel[nd];
+            d = 0.0;
+        }
+        Fh[0] = 0.5 * ((FL + FR) - (harten(a, d) * (uR - uL)));
+        return;
+    }
+    if (P->flux == OC_FLUX_EC) {
+        /* Tadmor's entropy-conservative flux for Burgers (entropy u^2 / 2) */
+        Fh[0] = (((uL * uL) + (uL * uR)) + (uR * uR)) / 6.0;
+        return;
+    }
     if (SL >= 0.0) { Fh[0] = FL; return; }
     if (SR <= 0.0) { Fh[0] = FR; return; }
     Fh[0] = (((SR * FL) - (SL * FR)) + ((SL * SR) * (uR - uL))) / (SR - SL);
@@ -277,10 +370,22 @@ static void reconstruct(int recon, double um, double u0, double up, double* minu
         double sigma = minmod(u0 - um, up - u0);
         *plus = u0 + (0.5 * sigma);
         *minus = u0 - (0.5 * sigma);
+    } else if (recon == OC_REC_ENO2) {
+        /* second-order ENO: the one-sided difference of smaller magnitude (left on a tie) */
+        double dl = u0 - um, dr = up - u0;
+        double sigma = (fabs(dl) <= fabs(dr)) ? dl : dr;
+        *plus = u0 + (0.5 * sigma);
+        *minus = u0 - (0.5 * sigma);
     } else {
         *plus = oc_weno3(um, u0, up);
         *minus = oc_weno3(up, u0, um);
     }
+}
+
+/* The face values (i - 1/2, i + 1/2) of one cell, for the pins. */
+void oc_reconstruct(int recon, double um, double u0, double up, double* minus, double* plus)
+{
+    reconstruct(recon, um, u0, up, minus, plus);
 }
 
 /* ---------------------------------------------------------------- one right-hand side */
