@@ -51,8 +51,18 @@ typedef enum {
 
 typedef enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1 } fv_bc;
 typedef enum { FV_EQ_ADVECTION = 0, FV_EQ_BURGERS = 1, FV_EQ_EULER = 2 } fv_eq_kind;
-typedef enum { FV_FLUX_RUSANOV = 0, FV_FLUX_HLL = 1, FV_FLUX_HLLC = 2 } fv_flux;
-typedef enum { FV_RECON_FIRST_ORDER = 0, FV_RECON_MUSCL_MINMOD = 1, FV_RECON_WENO3 = 2 } fv_recon;
+/* Numerical fluxes (Section 2.1 names HLLC, Godunov, Rusanov, Roe and entropy-conservative
+ * fluxes): Rusanov (local Lax--Friedrichs); HLL and HLLC with Davis wave speeds; Roe with
+ * Roe's average state and Harten's entropy fix on the acoustic waves (for Burgers the Roe
+ * speed (uL + uR)/2 with the fix over a rarefaction fan, for advection upwinding); EC,
+ * Tadmor's entropy-conservative flux (uL^2 + uL uR + uR^2)/6, Burgers only. */
+typedef enum { FV_FLUX_RUSANOV = 0, FV_FLUX_HLL = 1, FV_FLUX_HLLC = 2, FV_FLUX_ROE = 3,
+               FV_FLUX_EC = 4 } fv_flux;
+/* Reconstructions (Section 2.1 names ENO and WENO): piecewise constant; MUSCL with the
+ * minmod limiter; third-order WENO; second-order ENO (the one-sided difference of smaller
+ * magnitude, the left one on a tie). Component-wise on the conserved variables. */
+typedef enum { FV_RECON_FIRST_ORDER = 0, FV_RECON_MUSCL_MINMOD = 1, FV_RECON_WENO3 = 2,
+               FV_RECON_ENO2 = 3 } fv_recon;
 typedef enum { FV_INT_FORWARD_EULER = 0, FV_INT_SSPRK2 = 1, FV_INT_SSPRK3 = 2 } fv_integrator;
 
 /* Uniform Cartesian grid on [lo, hi] per axis (Section 2.1: cells i with averages U_i).

@@ -45,7 +45,8 @@ static std::vector<RegEntry>& registry()
     std::call_once(once, [] {
         const RegEntry* (*units[])(int*) = {unit_euler1d, unit_euler2d, unit_euler2d_hot,
                                             unit_euler3d, unit_euler3d_hot, unit_scalar1d,
-                                            unit_scalar2d, unit_scalar3d};
+                                            unit_scalar2d, unit_scalar3d, unit_more1d,
+                                            unit_more2d, unit_more3d};
         for (auto u : units) {
             int n = 0;
             const RegEntry* t = u(&n);
@@ -160,8 +161,10 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     if (st) return st;
     if (!eq) return fail(FV_EINVAL, "equation is NULL");
     if (eq->kind < 0 || eq->kind > 2) return fail(FV_EINVAL, "unknown equation kind");
-    if (flux < 0 || flux > 2) return fail(FV_EINVAL, "unknown flux");
-    if (recon < 0 || recon > 2) return fail(FV_EINVAL, "unknown reconstruction");
+    if (flux < 0 || flux > 4) return fail(FV_EINVAL, "unknown flux");
+    if (recon < 0 || recon > 3) return fail(FV_EINVAL, "unknown reconstruction");
+    if (flux == FV_FLUX_EC && eq->kind != FV_EQ_BURGERS)
+        return fail(FV_ENOTSUP, "the entropy-conservative flux is offered for Burgers only");
     if (integrator < 0 || integrator > 2) return fail(FV_EINVAL, "unknown integrator");
     if (flux == FV_FLUX_HLLC && eq->kind != FV_EQ_EULER)
         return fail(FV_ENOTSUP, "HLLC needs the Euler equations");

@@ -71,6 +71,73 @@ __device__ __forceinline__ void euler_flux(const double* U, const EulerPrim<DIM>
     F[DIM + 1] = (U[DIM + 1] + w.p) * un;
 }
 
+// Harten's entropy fix of a wave speed l with fan width d >= 0.
+__device__ __forceinline__ double harten_fix(double l, double d)
+{
+    const double al = fabs(l);
+    return (al >= d) ? al : (((l * l) + (d * d)) / (2.0 * d));
+}
+
+// Roe's flux: half the sum of the two physical fluxes minus half the sum over the
+// characteristic fields of the Roe-average Jacobian, |speed| x strength x eigenvector, taken
+// in the order acoustic (u - a), entropy (u), shear (tangential axes ascending), acoustic
+// (u + a). Average state: velocity and total enthalpy weighted by sqrt(rho), sound speed from
+// (gamma - 1)(H - |u|^2 / 2), density sqrt(rho_L rho_R). Harten's fix acts on the acoustic
+// speeds with half the jump of the one-sided characteristic speeds as fan width.
+template <int DIM>
+__device__ __forceinline__ void roe_flux(const double* UL, const double* UR, const EulerPrim<DIM>& wl,
+                                         const EulerPrim<DIM>& wr, const double* FL, const double* FR,
+                                         int nd, double* Fh, const Phys& ph)
+{
+    const double sqL = sqrt(UL[0]);
+    const double sqR = sqrt(UR[0]);
+    const double wsum = sqL + sqR;
+    const double hL = (UL[DIM + 1] + wl.p) * wl.ir;
+    const double hR = (UR[DIM + 1] + wr.p) * wr.ir;
+    double ua[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) ua[k] = ((sqL * wl.u[k]) + (sqR * wr.u[k])) / wsum;
+    const double ha = ((sqL * hL) + (sqR * hR)) / wsum;
+    double usq = ua[0] * ua[0];
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) usq = usq + (ua[k] * ua[k]);
+    const double csq = ph.gm1 * (ha - (0.5 * usq));
+    const double ca = sqrt(csq);
+    const double rhoa = sqL * sqR;
+    const double una = pick<DIM>(ua, nd);
+    const double unL = pick<DIM>(wl.u, nd), unR = pick<DIM>(wr.u, nd);
+    const double jr = UR[0] - UL[0];
+    const double jp = wr.p - wl.p;
+    const double jun = unR - unL;
+    const double rc = rhoa * ca;
+    const double s1 = (jp - (rc * jun)) / (2.0 * csq);    // strengths
+    const double s2 = jr - (jp / csq);
+    const double s3 = (jp + (rc * jun)) / (2.0 * csq);
+    const double fan1 = 0.5 * vmax(0.0, (unR - wr.c) - (unL - wl.c));
+    const double fan3 = 0.5 * vmax(0.0, (unR + wr.c) - (unL + wl.c));
+    const double g1 = harten_fix(una - ca, fan1) * s1;    // |speed| x strength
+    const double g2 = fabs(una) * s2;
+    const double g3 = harten_fix(una + ca, fan3) * s3;
+    double gs[DIM];                                        // shear fields
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) gs[k] = fabs(una) * (rhoa * (wr.u[k] - wl.u[k]));
+    double diss[DIM + 2];
+    diss[0] = (g1 + g2) + g3;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const bool n = (k == nd);
+        double t = (g1 * (n ? (ua[k] - ca) : ua[k])) + (g2 * ua[k]);
+        t = n ? t : (t + gs[k]);
+        diss[1 + k] = t + (g3 * (n ? (ua[k] + ca) : ua[k]));
+    }
+    double te = (g1 * (ha - (una * ca))) + (g2 * (0.5 * usq));
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) te = (k == nd) ? te : (te + (gs[k] * ua[k]));
+    diss[DIM + 1] = te + (g3 * (ha + (una * ca)));
+#pragma unroll
+    for (int q = 0; q < DIM + 2; ++q) Fh[q] = 0.5 * ((FL[q] + FR[q]) - diss[q]);
+}
+
 // Numerical flux of the Euler equations across a face with normal axis nd.
 template <int DIM, int FLUX>
 __device__ __forceinline__ void euler_numflux(const double* UL, const double* UR, int nd, double* Fh,
@@ -88,6 +155,10 @@ __device__ __forceinline__ void euler_numflux(const double* UL, const double* UR
         const double s = vmax(fabs(uL) + wl.c, fabs(uR) + wr.c);
 #pragma unroll
         for (int q = 0; q < NF; ++q) Fh[q] = 0.5 * ((FL[q] + FR[q]) - (s * (UR[q] - UL[q])));
+        return;
+    }
+    if (FLUX == FLUX_ROE) {
+        roe_flux<DIM>(UL, UR, wl, wr, FL, FR, nd, Fh, ph);
         return;
     }
     // Davis wave-speed estimates
@@ -160,6 +231,14 @@ __device__ __forceinline__ double scalar_numflux(double uL, double uR, int nd, c
         SR = a;
     }
     if (FLUX == FLUX_RUSANOV) return 0.5 * ((FL + FR) - (s * (uR - uL)));
+    if (FLUX == FLUX_ROE) {
+        // Roe speed: the mean for Burgers, with the fix over a rarefaction fan; the velocity
+        // for advection (plain upwinding)
+        const double a = (EQ == EQ_BURGERS) ? (0.5 * (uL + uR)) : SL;
+        const double fan = (EQ == EQ_BURGERS) ? (0.5 * vmax(0.0, uR - uL)) : 0.0;
+        return 0.5 * ((FL + FR) - (harten_fix(a, fan) * (uR - uL)));
+    }
+    if (FLUX == FLUX_EC) return (((uL * uL) + (uL * uR)) + (uR * uR)) / 6.0;   // Burgers
     const double mid = (((SR * FL) - (SL * FR)) + ((SL * SR) * (uR - uL))) / (SR - SL);
     return (SL >= 0.0) ? FL : ((SR <= 0.0) ? FR : mid);
 }
@@ -211,6 +290,11 @@ __device__ __forceinline__ void reconstruct(double a, double b, double c, double
     } else if (RECON == REC_MUSCL) {
         uL = b + (0.5 * minmod(b - a, c - b));
         uR = c - (0.5 * minmod(c - b, d - c));
+    } else if (RECON == REC_ENO2) {
+        // the one-sided difference of smaller magnitude (the left one on a tie)
+        const double lb = b - a, rb = c - b, rc = d - c;
+        uL = b + (0.5 * ((fabs(lb) <= fabs(rb)) ? lb : rb));
+        uR = c - (0.5 * ((fabs(rb) <= fabs(rc)) ? rb : rc));
     } else {
         // uL = weno3(a, b, c), uR = weno3(d, c, b). Both use the indicator of (b, c) and the
         // candidate (b + c)/2: (b - c)^2 equals (c - b)^2 and b + c equals c + b bit for bit,

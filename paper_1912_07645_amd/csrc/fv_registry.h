@@ -22,6 +22,9 @@ FV_DECLARE_UNIT(unit_euler3d_hot)
 FV_DECLARE_UNIT(unit_scalar1d)
 FV_DECLARE_UNIT(unit_scalar2d)
 FV_DECLARE_UNIT(unit_scalar3d)
+FV_DECLARE_UNIT(unit_more1d)
+FV_DECLARE_UNIT(unit_more2d)
+FV_DECLARE_UNIT(unit_more3d)
 
 }  // namespace fvk
 
