@@ -11,7 +11,7 @@ state already resident in HBM), the roofline of the dominant kernel (the stage k
 timed with HIP events on the library's stream over its own launches) and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh3d|mc|sod]
+    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh3d|mc|sod]
     python bench.py --copy-calibration     # plain copy of known size, for rocprof counters
 """
 from __future__ import annotations
@@ -42,14 +42,16 @@ WENO3_PER_COMPONENT = 43        # both face values of one component (shared indi
 EULER_PRIM = {1: 31, 2: 34, 3: 37}            # primitives of one face state
 EULER_FLUX = {1: 4, 2: 5, 3: 6}                # physical flux of one face state
 HLLC = {1: 76, 2: 85, 3: 94}                   # wave speeds, contact, star state, selects
+ROE = {1: 193, 2: 222, 3: 251}                 # Roe averages, strengths, entropy fix, dissipation
 DIVERGENCE_RK = {1: 3 + 5, 2: 6 + 5, 3: 9 + 5}  # per component: flux difference sum, stage
 CFL_CELL = {1: 45, 2: 47, 3: 55}              # per cell, last stage only
 
 
-def lane_ops_per_cell_stage(dim: int, integrator: str) -> float:
-    """WENO3 + HLLC Euler: algorithmic FP64 lane-ops per cell per Runge--Kutta stage."""
+def lane_ops_per_cell_stage(dim: int, integrator: str, flux: str = "hllc") -> float:
+    """WENO3 + HLLC (or Roe) Euler: algorithmic FP64 lane-ops per cell per Runge--Kutta stage."""
     nf = dim + 2
-    face = nf * WENO3_PER_COMPONENT + 2 * (EULER_PRIM[dim] + EULER_FLUX[dim]) + HLLC[dim]
+    riemann = HLLC[dim] if flux == "hllc" else ROE[dim]
+    face = nf * WENO3_PER_COMPONENT + 2 * (EULER_PRIM[dim] + EULER_FLUX[dim]) + riemann
     stages = {"forward_euler": 1, "ssprk2": 2, "ssprk3": 3}[integrator]
     return dim * face + nf * DIVERGENCE_RK[dim] + CFL_CELL[dim] / stages
 
@@ -72,6 +74,9 @@ WORKLOADS = {
     "kh3d": dict(name="kh3d_512^3_weno3_hllc_ssprk3", dim=3, n=512, flux="hllc",
                  recon="weno3", integrator="ssprk3", cfl=0.4, batch=1, seed=1914,
                  steps=20, warmup=2, cpu_steps=1),
+    "kh2d_roe": dict(name="kh2d_1024x1024_weno3_roe_ssprk3", dim=2, n=1024, flux="roe",
+                     recon="weno3", integrator="ssprk3", cfl=0.4, batch=1, seed=1912,
+                     steps=1000, warmup=50, cpu_steps=4),
     "mc": dict(name="kh2d_256x256_x1024_samples_weno3_hllc_ssprk3", dim=2, n=256, flux="hllc",
                recon="weno3", integrator="ssprk3", cfl=0.4, batch=1024, seed=1912,
                steps=50, warmup=5, cpu_steps=2),
@@ -435,15 +440,15 @@ def measure(a, w, steps=None, warmup=None):
     hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_per_launch,
            "traffic": measured_traffic(a.workload)}
-    if w["recon"] == "weno3" and w["flux"] == "hllc":
-        ops_launch = lane_ops_per_cell_stage(w["dim"], w["integrator"]) * cells * B
+    if w["recon"] == "weno3" and w["flux"] in ("hllc", "roe"):
+        ops_launch = lane_ops_per_cell_stage(w["dim"], w["integrator"], w["flux"]) * cells * B
         alu_tops = ops_launch / avg_launch_s / 1e12
         roof = {"bound": "alu", "achieved": alu_tops, "peak": FP64_LANE_OPS_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": alu_tops * 1e12 / FP64_LANE_OPS_PEAK,
                 "traffic": hbm["traffic"], "kernel": "stage_kernel",
                 "avg_launch_us": avg_launch_s * 1e6,
                 "algorithmic_fp64_ops_per_launch": ops_launch,
-                "fp64_ops_per_cell_stage": lane_ops_per_cell_stage(w["dim"], w["integrator"]),
+                "fp64_ops_per_cell_stage": lane_ops_per_cell_stage(w["dim"], w["integrator"], w["flux"]),
                 "hbm": hbm}
     else:
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
