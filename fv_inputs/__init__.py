@@ -31,7 +31,7 @@ __all__ = [
     "sod_state", "riemann_state_1d", "kh2d_state", "kh3d_state", "constant_state",
     "random_smooth_state", "sine_state_scalar", "cell_centres", "mlmc_inputs",
     "kh2d_state_and_jacobian", "primitive_polynomials", "sobol_points",
-    "kh_coefficients_qmc",
+    "kh_coefficients_qmc", "swe_dam_break_1d", "swe_circular_dam_break", "random_smooth_swe",
 ]
 
 
@@ -279,6 +279,42 @@ def kh3d_state(n: int, cx, phix, cz, phiz, gamma: float = 1.4, a: float = 0.01) 
             for q in range(5):
                 out[s, q, k] = uout[q] + f * (uin[q] - uout[q])
     return out
+
+
+def swe_dam_break_1d(n: int, hL: float = 2.0, hR: float = 1.0, x0: float = 0.5) -> np.ndarray:
+    """Shallow-water dam break on [0, 1]: depth hL left of x0, hR right of it, at rest.
+    Fields (h, hu): [1][2][1][1][n]."""
+    x = cell_centres(n)
+    U = np.zeros((1, 2, 1, 1, n))
+    U[0, 0, 0, 0] = np.where(x < x0, hL, hR)
+    return U
+
+
+def swe_circular_dam_break(n: int, h_in: float = 2.0, h_out: float = 1.0, r0: float = 0.2,
+                           batch: int = 1) -> np.ndarray:
+    """Shallow water on the periodic unit square: depth h_in inside the circle of radius r0
+    about the centre (cell centres decide), h_out outside, at rest. Fields (h, hu, hv):
+    [batch][3][1][n][n]."""
+    x = cell_centres(n)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    h = np.where((X - 0.5) ** 2 + (Y - 0.5) ** 2 < r0 * r0, h_in, h_out)
+    U = np.zeros((batch, 3, 1, n, n))
+    U[:, 0, 0] = h
+    return U
+
+
+def random_smooth_swe(seed: int, shape_cells, dim: int, batch: int = 1) -> np.ndarray:
+    """Smooth periodic shallow-water data: h = 1 + 0.2 (low Fourier modes, |.| < 1) and
+    velocities of size 0.3, as (h, hu[, hv]) [batch][dim + 1][nz][ny][nx]."""
+    E = random_smooth_state(seed, shape_cells, dim, batch=batch)
+    rho = E[:, 0]
+    h = 1.0 + 0.2 * (rho - rho.mean()) / (np.abs(rho - rho.mean()).max() + 1e-300)
+    U = np.zeros((batch, dim + 1) + tuple(shape_cells))
+    U[:, 0] = h
+    for k in range(dim):
+        vel = E[:, 1 + k] / rho
+        U[:, 1 + k] = h * 0.3 * vel / (np.abs(vel).max() + 1e-300)
+    return U
 
 
 def constant_state(shape_cells, values, batch: int = 1) -> np.ndarray:

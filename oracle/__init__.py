@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "fv_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
 _SO = os.path.join(_BUILD, "liboracle.so")
 
-EQ = {"advection": 0, "burgers": 1, "euler": 2}
+EQ = {"advection": 0, "burgers": 1, "euler": 2, "swe": 3}
 FLUX = {"rusanov": 0, "hll": 1, "hllc": 2, "roe": 3, "ec": 4}
 RECON = {"first_order": 0, "muscl_minmod": 1, "weno3": 2, "eno2": 3}
 INTEGRATOR = {"forward_euler": 0, "ssprk2": 1, "ssprk3": 2}
@@ -36,7 +36,7 @@ class OcProblem(C.Structure):
         ("dim", C.c_int32), ("eq", C.c_int32), ("flux", C.c_int32), ("recon", C.c_int32),
         ("integrator", C.c_int32), ("bc", C.c_int32 * 3), ("n", C.c_int64 * 3),
         ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("gamma", C.c_double),
-        ("vel", C.c_double * 3),
+        ("vel", C.c_double * 3), ("grav", C.c_double),
     ]
 
 
@@ -119,6 +119,7 @@ class Problem:
     hi: tuple = (1.0, 1.0, 1.0)
     gamma: float = 1.4
     vel: tuple = (0.0, 0.0, 0.0)
+    gravity: float = 9.81
     _c: OcProblem = field(default=None, init=False, repr=False)
 
     def __post_init__(self):
@@ -137,6 +138,7 @@ class Problem:
             c.hi[k] = float(self.hi[k]) if k < len(self.hi) else 1.0
             c.vel[k] = float(self.vel[k]) if k < len(self.vel) else 0.0
         c.gamma = float(self.gamma)
+        c.grav = float(self.gravity)
         self._c = c
 
     @property
@@ -145,7 +147,7 @@ class Problem:
 
     @property
     def nfields(self) -> int:
-        return self.dim + 2 if self.eq == "euler" else 1
+        return {"euler": self.dim + 2, "swe": self.dim + 1}.get(self.eq, 1)
 
     @property
     def cells(self) -> int:

@@ -9,7 +9,8 @@
  *
  * What it computes:
  *   - the conservation law u_t + div F(u) = 0 (eq. 1.1) for linear advection, Burgers and
- *     the compressible Euler equations (gamma law) in 1, 2 or 3 space dimensions;
+ *     the compressible Euler equations (gamma law) in 1, 2 or 3 space dimensions, and the
+ *     shallow-water equations (h, hu; flux hu u + g h^2 / 2) in 1 or 2;
  *   - its semi-discrete finite-volume form (eq. 2.1): d/dt U_i = -sum_k (F_{i+1/2 e_k} -
  *     F_{i-1/2 e_k}) / dx_k, with the numerical fluxes (Rusanov, HLL, HLLC), the
  *     reconstructions (piecewise constant, MUSCL with minmod, third-order WENO) and the SSP
@@ -60,7 +61,7 @@
 
 /* ---------------------------------------------------------------- problem description */
 
-enum { OC_EQ_ADVECTION = 0, OC_EQ_BURGERS = 1, OC_EQ_EULER = 2 };
+enum { OC_EQ_ADVECTION = 0, OC_EQ_BURGERS = 1, OC_EQ_EULER = 2, OC_EQ_SWE = 3 };
 enum { OC_FLUX_RUSANOV = 0, OC_FLUX_HLL = 1, OC_FLUX_HLLC = 2, OC_FLUX_ROE = 3, OC_FLUX_EC = 4 };
 enum { OC_REC_FIRST = 0, OC_REC_MUSCL = 1, OC_REC_WENO3 = 2, OC_REC_ENO2 = 3 };
 enum { OC_INT_FE = 0, OC_INT_RK2 = 1, OC_INT_RK3 = 2 };
@@ -82,11 +83,14 @@ typedef struct {
     double hi[3];
     double gamma;
     double vel[3];
+    double grav;      /* shallow water: gravitational acceleration g */
 } oc_problem;
 
 int oc_num_fields(const oc_problem* P)
 {
-    return P->eq == OC_EQ_EULER ? P->dim + 2 : 1;
+    if (P->eq == OC_EQ_EULER) return P->dim + 2;
+    if (P->eq == OC_EQ_SWE) return P->dim + 1;
+    return 1;
 }
 
 static int64_t cells_of(const oc_problem* P)
@@ -111,13 +115,17 @@ int oc_validate(const oc_problem* P)
         if (k < P->dim && !(P->hi[k] > P->lo[k])) return OC_EINVAL;
         if (P->bc[k] != OC_BC_PERIODIC && P->bc[k] != OC_BC_TRANSMISSIVE) return OC_EINVAL;
     }
-    if (P->eq < 0 || P->eq > 2) return OC_EINVAL;
+    if (P->eq < 0 || P->eq > 3) return OC_EINVAL;
     if (P->flux < 0 || P->flux > 4) return OC_EINVAL;
     if (P->recon < 0 || P->recon > 3) return OC_EINVAL;
     if (P->integrator < 0 || P->integrator > 2) return OC_EINVAL;
     if (P->flux == OC_FLUX_HLLC && P->eq != OC_EQ_EULER) return OC_ENOTSUP;
     if (P->flux == OC_FLUX_EC && P->eq != OC_EQ_BURGERS) return OC_ENOTSUP;
     if (P->eq == OC_EQ_EULER && !(P->gamma > 1.0)) return OC_EINVAL;
+    if (P->eq == OC_EQ_SWE) {
+        if (!(P->grav > 0.0)) return OC_EINVAL;
+        if (P->dim > 2) return OC_ENOTSUP;
+    }
     return OC_OK;
 }
 
@@ -231,12 +239,98 @@ static void roe_euler(const double* UL, const double* UR, const oc_prim* wl, con
     for (int q = 0; q < dim + 2; ++q) Fh[q] = 0.5 * ((FL[q] + FR[q]) - D[q]);
 }
 
+/* Shallow water (h, hu_1..hu_d): velocity u_k = hu_k * (1/h), celerity c = sqrt(g h), flux
+ * along nd (hu_nd, hu_k u_nd + (k == nd) g h^2 / 2). */
+typedef struct {
+    double ih;        /* 1 / h */
+    double u[2];
+    double c;
+} oc_swe;
+
+static oc_swe swe_prim(const double* U, int dim, double g)
+{
+    oc_swe w;
+    w.ih = 1.0 / U[0];
+    w.u[0] = w.u[1] = 0.0;
+    for (int k = 0; k < dim; ++k) w.u[k] = U[1 + k] * w.ih;
+    w.c = sqrt(g * U[0]);
+    return w;
+}
+
+static void swe_flux(const double* U, const oc_swe* w, int dim, int nd, double g, double* F)
+{
+    const double un = w->u[nd];
+    const double hp = 0.5 * (g * (U[0] * U[0]));
+    F[0] = U[1 + nd];
+    for (int k = 0; k < dim; ++k) F[1 + k] = (k == nd) ? ((U[1 + k] * un) + hp) : (U[1 + k] * un);
+}
+
+/* Roe's flux for shallow water: average velocity weighted by sqrt(h), celerity
+ * c~ = sqrt(g (h_L + h_R) / 2), strengths alpha_1,2 = (dh -+ (d(hu_n) - u~_n dh) / c~) / 2
+ * on the fields u~_n -+ c~ with eigenvectors (1, u~ -+ c~ n), shear strengths
+ * d(hu_k) - u~_k dh on the fields u~_n with eigenvectors (0, e_k); Harten's fix on the two
+ * gravity waves with fan widths max(0, l(U_R) - l(U_L)) / 2; fields summed in the order
+ * u - c, shear (k ascending), u + c. */
+static void roe_swe(const double* UL, const double* UR, const oc_swe* wl, const oc_swe* wr,
+                    const double* FL, const double* FR, int dim, int nd, double g, double* Fh)
+{
+    const double sL = sqrt(UL[0]), sR = sqrt(UR[0]);
+    const double ssum = sL + sR;
+    double ut[2] = {0.0, 0.0};
+    for (int k = 0; k < dim; ++k) ut[k] = ((sL * wl->u[k]) + (sR * wr->u[k])) / ssum;
+    const double ct = sqrt(g * (0.5 * (UL[0] + UR[0])));
+    const double un = ut[nd];
+    const double dh = UR[0] - UL[0];
+    const double dq = (UR[1 + nd] - UL[1 + nd]) - (un * dh);
+    const double alpha1 = 0.5 * (dh - (dq / ct));
+    const double alpha2 = 0.5 * (dh + (dq / ct));
+    const double d1 = 0.5 * dmax(0.0, (wr->u[nd] - wr->c) - (wl->u[nd] - wl->c));
+    const double d2 = 0.5 * dmax(0.0, (wr->u[nd] + wr->c) - (wl->u[nd] + wl->c));
+    const double w1 = harten(un - ct, d1) * alpha1;
+    const double w2 = harten(un + ct, d2) * alpha2;
+    double D[OC_MAXF];
+    D[0] = w1 + w2;
+    for (int k = 0; k < dim; ++k) {
+        double t = w1 * ((k == nd) ? (un - ct) : ut[k]);
+        if (k != nd) t = t + (fabs(un) * ((UR[1 + k] - UL[1 + k]) - (ut[k] * dh)));
+        D[1 + k] = t + (w2 * ((k == nd) ? (un + ct) : ut[k]));
+    }
+    for (int q = 0; q < dim + 1; ++q) Fh[q] = 0.5 * ((FL[q] + FR[q]) - D[q]);
+}
+
 /* Numerical flux across a face with normal direction nd, from the reconstructed states
  * UL (left of the face) and UR (right of the face). */
 void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const double* UR,
                        double* Fh)
 {
     const int nf = oc_num_fields(P);
+    if (P->eq == OC_EQ_SWE) {
+        const int dim = P->dim;
+        const double g = P->grav;
+        oc_swe wl = swe_prim(UL, dim, g);
+        oc_swe wr = swe_prim(UR, dim, g);
+        double FL[OC_MAXF], FR[OC_MAXF];
+        swe_flux(UL, &wl, dim, nd, g, FL);
+        swe_flux(UR, &wr, dim, nd, g, FR);
+        const double uL = wl.u[nd], uR = wr.u[nd];
+        if (P->flux == OC_FLUX_RUSANOV) {
+            double s = dmax(fabs(uL) + wl.c, fabs(uR) + wr.c);
+            for (int q = 0; q < nf; ++q)
+                Fh[q] = 0.5 * ((FL[q] + FR[q]) - (s * (UR[q] - UL[q])));
+            return;
+        }
+        if (P->flux == OC_FLUX_ROE) {
+            roe_swe(UL, UR, &wl, &wr, FL, FR, dim, nd, g, Fh);
+            return;
+        }
+        double SL = dmin(uL - wl.c, uR - wr.c);
+        double SR = dmax(uL + wl.c, uR + wr.c);
+        if (SL >= 0.0) { for (int q = 0; q < nf; ++q) Fh[q] = FL[q]; return; }
+        if (SR <= 0.0) { for (int q = 0; q < nf; ++q) Fh[q] = FR[q]; return; }
+        for (int q = 0; q < nf; ++q)
+            Fh[q] = (((SR * FL[q]) - (SL * FR[q])) + ((SL * SR) * (UR[q] - UL[q]))) / (SR - SL);
+        return;
+    }
     if (P->eq == OC_EQ_EULER) {
         const int dim = P->dim;
         const double gamma = P->gamma;
@@ -533,7 +627,7 @@ int oc_rhs(const oc_problem* P, const double* U, double* rhs)
 /* ---------------------------------------------------------------- wave speed / CFL */
 
 /* Maximum over cells and directions of (|u_d| + c) / dx_d for one sample, and whether any
- * cell is non-physical (rho <= 0, p <= 0 or a non-finite component). */
+ * cell is non-physical (rho <= 0, p <= 0, h <= 0 or a non-finite component). */
 void oc_max_speed(const oc_problem* P, const double* U, double* M_out, int* bad_out)
 {
     const int nf = oc_num_fields(P);
@@ -552,6 +646,13 @@ void oc_max_speed(const oc_problem* P, const double* U, double* M_out, int* bad_
         if (P->eq == OC_EQ_EULER) {
             oc_prim w = euler_prim(V, dim, gamma, gm1);
             if (!(V[0] > 0.0) || !(w.p > 0.0)) bad = 1;
+            for (int d = 0; d < dim; ++d) {
+                double a = (fabs(w.u[d]) + w.c) * inv_dx(P, d);
+                m = (d == 0) ? a : dmax(m, a);
+            }
+        } else if (P->eq == OC_EQ_SWE) {
+            oc_swe w = swe_prim(V, dim, P->grav);
+            if (!(V[0] > 0.0)) bad = 1;
             for (int d = 0; d < dim; ++d) {
                 double a = (fabs(w.u[d]) + w.c) * inv_dx(P, d);
                 m = (d == 0) ? a : dmax(m, a);
@@ -686,11 +787,20 @@ int oc_num_quantities(const oc_problem* P)
     return oc_num_fields(P);
 }
 
-/* q[quantity][cells] of one sample: rho, u_k = m_k * (1/rho), E; or the scalar itself. */
+/* q[quantity][cells] of one sample: rho, u_k = m_k * (1/rho), E; shallow water h,
+ * u_k = hu_k * (1/h); or the scalar itself. */
 void oc_quantities(const oc_problem* P, const double* U, double* q)
 {
     const int nf = oc_num_fields(P);
     const int64_t N = cells_of(P);
+    if (P->eq == OC_EQ_SWE) {
+        for (int64_t c = 0; c < N; ++c) {
+            double ih = 1.0 / U[c];
+            q[c] = U[c];
+            for (int k = 0; k < P->dim; ++k) q[(1 + k) * N + c] = U[(1 + k) * N + c] * ih;
+        }
+        return;
+    }
     if (P->eq != OC_EQ_EULER) {
         memcpy(q, U, sizeof(double) * (size_t)N);
         return;
@@ -796,6 +906,10 @@ static int pdf_bin(double v, double lo, double hi, int32_t nbins)
 static double cell_quantity(const oc_problem* P, const double* U, int64_t c, int qi)
 {
     const int64_t N = cells_of(P);
+    if (P->eq == OC_EQ_SWE && qi > 0) {
+        double ih = 1.0 / U[c];
+        return U[qi * N + c] * ih;
+    }
     if (P->eq != OC_EQ_EULER || qi == 0 || qi == oc_num_fields(P) - 1) return U[qi * N + c];
     double ir = 1.0 / U[c];
     return U[qi * N + c] * ir;

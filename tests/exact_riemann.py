@@ -115,3 +115,32 @@ def burgers_sample(uL, uR, xi):
         s = 0.5 * (uL + uR)
         return np.where(xi < s, uL, uR)
     return np.where(xi <= uL, uL, np.where(xi >= uR, uR, xi))
+
+
+def swe_dam_break(hL, hR, xi, g=9.81):
+    """Exact wet-bed dam break of the shallow-water equations (h_L > h_R > 0, both at rest) at
+    xi = (x - x0) / t: a left rarefaction and a right shock around the middle state (h_m, u_m).
+    The rarefaction gives u_m = 2 (c_L - c_m) (c = sqrt(g h)), the shock
+    u_m = (h_m - h_R) sqrt(g (1/h_m + 1/h_R) / 2); h_m is found by bisection. Returns
+    (h, u, h_m, u_m, shock speed)."""
+    cL = np.sqrt(g * hL)
+
+    def f(hm):
+        return 2.0 * (cL - np.sqrt(g * hm)) - (hm - hR) * np.sqrt(0.5 * g * (1.0 / hm + 1.0 / hR))
+
+    lo, hi = hR, hL
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    hm = 0.5 * (lo + hi)
+    cm = np.sqrt(g * hm)
+    um = 2.0 * (cL - cm)
+    S = hm * um / (hm - hR)
+    xi = np.asarray(xi, dtype=np.float64)
+    c_fan = (2.0 * cL - xi) / 3.0
+    h = np.where(xi < -cL, hL, np.where(xi < um - cm, c_fan * c_fan / g, np.where(xi < S, hm, hR)))
+    u = np.where(xi < -cL, 0.0, np.where(xi < um - cm, 2.0 * (cL - c_fan), np.where(xi < S, um, 0.0)))
+    return h, u, hm, um, S
