@@ -50,7 +50,8 @@ typedef enum {
 } fv_status;
 
 typedef enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1 } fv_bc;
-typedef enum { FV_EQ_ADVECTION = 0, FV_EQ_BURGERS = 1, FV_EQ_EULER = 2 } fv_eq_kind;
+typedef enum { FV_EQ_ADVECTION = 0, FV_EQ_BURGERS = 1, FV_EQ_EULER = 2,
+               FV_EQ_SHALLOW_WATER = 3 } fv_eq_kind;
 /* Numerical fluxes (Section 2.1 names HLLC, Godunov, Rusanov, Roe and entropy-conservative
  * fluxes): Rusanov (local Lax--Friedrichs); HLL and HLLC with Davis wave speeds; Roe with
  * Roe's average state and Harten's entropy fix on the acoustic waves (for Burgers the Roe
@@ -78,12 +79,16 @@ typedef struct {
 } fv_grid;
 
 /* The flux function F of eq. (1.1): linear advection F = a u (velocity[k] = a_k), Burgers
- * F = u^2/2 in every direction, or the compressible Euler equations with the gamma law
- * p = (gamma - 1)(E - |m|^2 / (2 rho)) (gamma > 1). */
+ * F = u^2/2 in every direction, the compressible Euler equations with the gamma law
+ * p = (gamma - 1)(E - |m|^2 / (2 rho)) (gamma > 1), or the shallow-water equations
+ * (h, hu_1..hu_dim) with flux along k (hu_k, hu u_k + g h^2 / 2 e_k), u = hu (1/h),
+ * gravity = g > 0, in 1D and 2D (a second workload family; the paper's framework is built
+ * for several equations, Section 2.1). */
 typedef struct {
     int32_t kind;          /* fv_eq_kind */
     double gamma;
     double velocity[3];
+    double gravity;        /* shallow water only */
 } fv_equation;
 
 typedef struct fv_solver fv_solver;   /* opaque, library-owned */
@@ -194,7 +199,8 @@ fv_status fv_profile_read(const fv_solver* solver, double* stage_ms, int64_t* st
 /* ------------------------------------------------------------------ statistics */
 
 /* Running Monte Carlo statistics (Section 2.2) on the solver's grid. Quantities: Euler
- * (rho, u_1..u_dim, E) with u_k = m_k * (1/rho); scalar equations the field itself.
+ * (rho, u_1..u_dim, E) with u_k = m_k * (1/rho); shallow water (h, u_1..u_dim) with
+ * u_k = hu_k * (1/h); scalar equations the field itself.
  * max_h >= 0 is the largest lag of the second-order structure function
  * S_q(h) = 1/(dim N) sum_axes sum_x (q(x + h e_axis) - q(x))^2 (periodic grids only,
  * max_h < n[k] on every axis; FV_ENOTSUP otherwise). */
@@ -237,7 +243,8 @@ fv_status fv_stats_destroy(fv_stats* stats);
 /* Point PDFs (Section 2.2 lists them among the statistics, after Fjordholm, Lye and Mishra):
  * for every cell points[i] (host int64 array of npoints cell indices, x fastest), the
  * histogram over the batch's samples of one quantity (as for fv_stats_create: Euler rho,
- * u_1..u_dim, E with u_k = m_k * (1/rho); scalar equations the field, quantity 0) at that
+ * u_1..u_dim, E with u_k = m_k * (1/rho); shallow water h, u_1..u_dim; scalar equations the
+ * field, quantity 0) at that
  * cell. nbins equal bins on [lo, hi): a value v in range goes to bin
  * floor(((v - lo) / (hi - lo)) * nbins) computed in FP64 in that order, or to the last bin
  * if that rounds to nbins. counts: device int64 [npoints][nbins + 2], ADDED to (the caller

@@ -46,7 +46,7 @@ static std::vector<RegEntry>& registry()
         const RegEntry* (*units[])(int*) = {unit_euler1d, unit_euler2d, unit_euler2d_hot,
                                             unit_euler3d, unit_euler3d_hot, unit_scalar1d,
                                             unit_scalar2d, unit_scalar3d, unit_more1d,
-                                            unit_more2d, unit_more3d};
+                                            unit_more2d, unit_more3d, unit_swe};
         for (auto u : units) {
             int n = 0;
             const RegEntry* t = u(&n);
@@ -160,7 +160,11 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     fv_status st = validate_grid(grid);
     if (st) return st;
     if (!eq) return fail(FV_EINVAL, "equation is NULL");
-    if (eq->kind < 0 || eq->kind > 2) return fail(FV_EINVAL, "unknown equation kind");
+    if (eq->kind < 0 || eq->kind > 3) return fail(FV_EINVAL, "unknown equation kind");
+    if (eq->kind == FV_EQ_SHALLOW_WATER) {
+        if (!(eq->gravity > 0.0) || !std::isfinite(eq->gravity)) return fail(FV_EINVAL, "gravity must be positive");
+        if (grid->dim > 2) return fail(FV_ENOTSUP, "the shallow-water equations are offered in 1D and 2D");
+    }
     if (flux < 0 || flux > 4) return fail(FV_EINVAL, "unknown flux");
     if (recon < 0 || recon > 3) return fail(FV_EINVAL, "unknown reconstruction");
     if (flux == FV_FLUX_EC && eq->kind != FV_EQ_BURGERS)
@@ -183,12 +187,13 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     s->flux = flux;
     s->recon = recon;
     s->integ = integrator;
-    s->nf = eq->kind == FV_EQ_EULER ? grid->dim + 2 : 1;
+    s->nf = eq->kind == FV_EQ_EULER ? grid->dim + 2 : (eq->kind == FV_EQ_SHALLOW_WATER ? grid->dim + 1 : 1);
     s->cells = grid->n[0] * grid->n[1] * grid->n[2];
     s->variant = 0;
     s->kern = kern;
     s->ph.gamma = eq->gamma;
     s->ph.gm1 = eq->gamma - 1.0;
+    s->ph.grav = eq->gravity;
     for (int k = 0; k < 3; ++k) {
         s->ph.vel[k] = eq->velocity[k];
         s->ph.inv_dx[k] = (double)grid->n[k] / (grid->hi[k] - grid->lo[k]);
@@ -889,7 +894,7 @@ extern "C" fv_status fv_stats_accumulate(fv_stats* st, const double* state, int6
     fv_status e = stream_enter(s);
     if (e) return e;
     hipStream_t str = s->stream;
-    const bool euler = s->eq.kind == FV_EQ_EULER;
+    const int qkind = quantity_kind(s);
     const int64_t per = (int64_t)s->nf * s->cells;
     int32_t n32[3] = {(int32_t)s->grid.n[0], (int32_t)s->grid.n[1], (int32_t)s->grid.n[2]};
     const int nblk = st->max_h > 0 ? sf_blocks_per_field(s->grid.dim, n32) : 0;
@@ -897,7 +902,7 @@ extern "C" fv_status fv_stats_accumulate(fv_stats* st, const double* state, int6
     for (int64_t b0 = 0; b0 < batch; b0 += st->chunk) {
         const int32_t nb = (int32_t)std::min<int64_t>(st->chunk, batch - b0);
         const double* chunk = state + b0 * per;
-        launch_welford(s->nf, euler, chunk, s->cells, nb, st->count, st->mean, st->m2,
+        launch_welford(s->nf, qkind, chunk, s->cells, nb, st->count, st->mean, st->m2,
                        st->max_h > 0 ? st->qbuf : nullptr, str);
         if (st->max_h > 0) {
             launch_sf_partial(st->qbuf, s->grid.dim, n32, st->nq, st->max_h, nb, st->partial, str);
@@ -940,11 +945,11 @@ extern "C" fv_status fv_stats_accumulate_diff(fv_stats* st, const double* fine,
     HIP_TRY(hipSetDevice(s->device));
     fv_status e = stream_enter(s);
     if (e) return e;
-    const bool euler = s->eq.kind == FV_EQ_EULER;
+    const int qkind = quantity_kind(s);
     const int64_t per_f = (int64_t)s->nf * s->cells, per_c = (int64_t)coarse->nf * coarse->cells;
     for (int64_t b0 = 0; b0 < batch; b0 += 1024) {
         const int32_t nb = (int32_t)std::min<int64_t>(1024, batch - b0);
-        launch_welford_diff(s->nf, euler, fine + b0 * per_f, coarse_state + b0 * per_c, geo, nb,
+        launch_welford_diff(s->nf, qkind, fine + b0 * per_f, coarse_state + b0 * per_c, geo, nb,
                             st->count, st->mean, st->m2, s->stream);
         HIP_TRY(hipGetLastError());
         st->count += nb;

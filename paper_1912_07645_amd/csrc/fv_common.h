@@ -7,7 +7,7 @@
 
 namespace fvk {
 
-enum { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2 };
+enum { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2, EQ_SWE = 3 };
 enum { FLUX_RUSANOV = 0, FLUX_HLL = 1, FLUX_HLLC = 2, FLUX_ROE = 3, FLUX_EC = 4 };
 enum { REC_FIRST = 0, REC_MUSCL = 1, REC_WENO3 = 2, REC_ENO2 = 3 };
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
@@ -23,6 +23,7 @@ struct Phys {
     double gm1;          // gamma - 1.0, computed at run time
     double vel[3];       // advection velocity
     double inv_dx[3];    // n_k / (hi_k - lo_k)
+    double grav;         // shallow water: g
 };
 
 // One group of samples on one grid (a batched launch covers one or more groups).

@@ -3,7 +3,7 @@
 // mean, variance and axis structure functions of fv_stats.hip.
 //
 // Quantities are those of the statistics: Euler (rho, u_1..u_dim, E) with u_k = m_k * (1/rho),
-// scalar equations the field itself.
+// shallow water (h, u_1..u_dim) with u_k = hu_k * (1/h), scalar equations the field itself.
 //
 // PDFs. One thread per (sample, point or pair) finds the bin of the quantity's value in FP64:
 // t = ((v - lo) / (hi - lo)) * nbins, bin floor(t), the last bin also taking a value that
@@ -30,10 +30,11 @@ namespace fvk {
 constexpr int kFnThreads = 256;
 constexpr int kShellMaxH = 64;
 
-__device__ __forceinline__ double quantity_at(const double* U, int64_t cells, int nf, int euler,
+// kind: 0 the field itself; 1 Euler (momenta over rho); 2 shallow water (momenta over h).
+__device__ __forceinline__ double quantity_at(const double* U, int64_t cells, int nf, int kind,
                                               int64_t c, int qi)
 {
-    if (!euler || qi == 0 || qi == nf - 1) return U[(int64_t)qi * cells + c];
+    if (kind == 0 || qi == 0 || (kind == 1 && qi == nf - 1)) return U[(int64_t)qi * cells + c];
     const double ir = 1.0 / U[c];
     return U[(int64_t)qi * cells + c] * ir;
 }
@@ -50,7 +51,7 @@ __device__ __forceinline__ int bin_of(double v, double lo, double hi, int nbins)
 struct PdfArgs {
     const double* state;         // [batch][nf][cells]
     int64_t cells;
-    int32_t nf, euler;
+    int32_t nf, kind;
     int64_t batch, n;            // samples; points (or pairs)
     const int64_t* cell;         // [n] points, or [n][2] pairs
     int32_t qa, qb, nbins, joint;
@@ -65,12 +66,12 @@ __global__ void __launch_bounds__(kFnThreads) pdf_kernel(const PdfArgs a)
     const int64_t b = t / a.n, i = t % a.n;
     const double* U = a.state + b * a.nf * a.cells;
     if (!a.joint) {
-        const int k = bin_of(quantity_at(U, a.cells, a.nf, a.euler, a.cell[i], a.qa), a.lo_a, a.hi_a, a.nbins);
+        const int k = bin_of(quantity_at(U, a.cells, a.nf, a.kind, a.cell[i], a.qa), a.lo_a, a.hi_a, a.nbins);
         const int slot = (k < 0) ? a.nbins : (k >= a.nbins ? a.nbins + 1 : k);
         atomicAdd(&a.counts[i * (a.nbins + 2) + slot], 1ull);
     } else {
-        const int ka = bin_of(quantity_at(U, a.cells, a.nf, a.euler, a.cell[2 * i], a.qa), a.lo_a, a.hi_a, a.nbins);
-        const int kb = bin_of(quantity_at(U, a.cells, a.nf, a.euler, a.cell[2 * i + 1], a.qb), a.lo_b, a.hi_b, a.nbins);
+        const int ka = bin_of(quantity_at(U, a.cells, a.nf, a.kind, a.cell[2 * i], a.qa), a.lo_a, a.hi_a, a.nbins);
+        const int kb = bin_of(quantity_at(U, a.cells, a.nf, a.kind, a.cell[2 * i + 1], a.qb), a.lo_b, a.hi_b, a.nbins);
         const int64_t per = (int64_t)a.nbins * a.nbins + 1;
         const bool in = ka >= 0 && ka < a.nbins && kb >= 0 && kb < a.nbins;
         atomicAdd(&a.counts[i * per + (in ? (int64_t)ka * a.nbins + kb : per - 1)], 1ull);
@@ -91,7 +92,7 @@ struct ShellArgs {
     int32_t n[3];
     int32_t tiles[3];
     int32_t ntiles;
-    int32_t nf, euler, nq, H, ball;
+    int32_t nf, kind, nq, H, ball;
     double* partial;       // [sample][q][H][ntiles]
 };
 
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(kFnThreads) shell_kernel(const ShellArgs a)
         const int32_t gx = wrap_mod(x0 + px - H, a.n[0]);
         const int32_t gy = (DIM >= 2) ? wrap_mod(y0 + py - HY, a.n[1]) : 0;
         const int32_t gz = (DIM >= 3) ? wrap_mod(z0 + pz - HZ, a.n[2]) : 0;
-        lq[e] = quantity_at(U, a.cells, a.nf, a.euler, ((int64_t)gz * a.n[1] + gy) * a.n[0] + gx, qi);
+        lq[e] = quantity_at(U, a.cells, a.nf, a.kind, ((int64_t)gz * a.n[1] + gy) * a.n[0] + gx, qi);
     }
     __syncthreads();
 
@@ -227,7 +228,7 @@ static int64_t shell_size(int dim, int h, int ball)
 
 using namespace fvk;
 
-static int32_t num_quantities(const fv_solver* s) { return s->eq.kind == FV_EQ_EULER ? s->nf : 1; }
+static int32_t num_quantities(const fv_solver* s) { return quantity_kind(s) ? s->nf : 1; }
 
 static fv_status pdf_common(const fv_solver* s, const double* state, int64_t batch, int32_t qa,
                             int32_t qb, int64_t n, const int64_t* cells_host, int per, double lo_a,
@@ -256,7 +257,7 @@ static fv_status pdf_common(const fv_solver* s, const double* state, int64_t bat
     a.state = state;
     a.cells = s->cells;
     a.nf = s->nf;
-    a.euler = s->eq.kind == FV_EQ_EULER;
+    a.kind = quantity_kind(s);
     a.batch = batch;
     a.n = n;
     a.cell = (const int64_t*)sm->scratch;
@@ -319,7 +320,7 @@ extern "C" fv_status fv_structure_shell(const fv_solver* s, const double* state,
         a.ntiles *= a.tiles[k];
     }
     a.nf = s->nf;
-    a.euler = s->eq.kind == FV_EQ_EULER;
+    a.kind = quantity_kind(s);
     a.nq = num_quantities(s);
     a.H = max_h;
     a.ball = ball;

@@ -15,7 +15,7 @@ namespace fvk {
 
 template <int DIM, int EQ>
 struct NumFields {
-    static constexpr int value = (EQ == EQ_EULER) ? DIM + 2 : 1;
+    static constexpr int value = (EQ == EQ_EULER) ? DIM + 2 : ((EQ == EQ_SWE) ? DIM + 1 : 1);
 };
 
 __device__ __forceinline__ double vmax(double a, double b) { return (a > b) ? a : b; }
@@ -210,6 +210,106 @@ __device__ __forceinline__ void euler_numflux(const double* UL, const double* UR
     }
 }
 
+// ---------------------------------------------------------------- shallow water
+
+// Shallow water (h, hu_1..hu_DIM): velocity hu_k (1/h), celerity sqrt(g h).
+template <int DIM>
+struct SwePrim {
+    double ih;
+    double u[DIM];
+    double c;
+};
+
+template <int DIM>
+__device__ __forceinline__ SwePrim<DIM> swe_prim(const double* U, const Phys& ph)
+{
+    SwePrim<DIM> w;
+    w.ih = 1.0 / U[0];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) w.u[k] = U[1 + k] * w.ih;
+    w.c = sqrt(ph.grav * U[0]);
+    return w;
+}
+
+// Physical flux along nd: (hu_nd, hu_k u_nd + [k == nd] g h^2 / 2).
+template <int DIM>
+__device__ __forceinline__ void swe_flux(const double* U, const SwePrim<DIM>& w, int nd, double* F,
+                                         const Phys& ph)
+{
+    const double un = pick<DIM>(w.u, nd);
+    const double hp = 0.5 * (ph.grav * (U[0] * U[0]));
+    F[0] = pick<DIM>(U + 1, nd);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const double a = U[1 + k] * un;
+        F[1 + k] = (k == nd) ? (a + hp) : a;
+    }
+}
+
+// Numerical flux of the shallow-water equations: Rusanov, HLL (Davis speeds u -+ c), or Roe
+// (velocity averaged with sqrt(h) weights, celerity sqrt(g (h_L + h_R) / 2); gravity waves
+// u -+ c with Harten's fix over half the jump of the one-sided speeds, shear waves at u;
+// fields in the order u - c, shear (axes ascending), u + c).
+template <int DIM, int FLUX>
+__device__ __forceinline__ void swe_numflux(const double* UL, const double* UR, int nd, double* Fh,
+                                            const Phys& ph)
+{
+    constexpr int NF = DIM + 1;
+    const SwePrim<DIM> wl = swe_prim<DIM>(UL, ph);
+    const SwePrim<DIM> wr = swe_prim<DIM>(UR, ph);
+    double FL[NF], FR[NF];
+    swe_flux<DIM>(UL, wl, nd, FL, ph);
+    swe_flux<DIM>(UR, wr, nd, FR, ph);
+    const double uL = pick<DIM>(wl.u, nd), uR = pick<DIM>(wr.u, nd);
+    if (FLUX == FLUX_RUSANOV) {
+        const double s = vmax(fabs(uL) + wl.c, fabs(uR) + wr.c);
+#pragma unroll
+        for (int q = 0; q < NF; ++q) Fh[q] = 0.5 * ((FL[q] + FR[q]) - (s * (UR[q] - UL[q])));
+        return;
+    }
+    if (FLUX == FLUX_ROE) {
+        const double sqL = sqrt(UL[0]);
+        const double sqR = sqrt(UR[0]);
+        const double wsum = sqL + sqR;
+        double ua[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ua[k] = ((sqL * wl.u[k]) + (sqR * wr.u[k])) / wsum;
+        const double ca = sqrt(ph.grav * (0.5 * (UL[0] + UR[0])));
+        const double una = pick<DIM>(ua, nd);
+        const double jh = UR[0] - UL[0];
+        const double jq = (pick<DIM>(UR + 1, nd) - pick<DIM>(UL + 1, nd)) - (una * jh);
+        const double s1 = 0.5 * (jh - (jq / ca));
+        const double s2 = 0.5 * (jh + (jq / ca));
+        const double fan1 = 0.5 * vmax(0.0, (uR - wr.c) - (uL - wl.c));
+        const double fan2 = 0.5 * vmax(0.0, (uR + wr.c) - (uL + wl.c));
+        const double g1 = harten_fix(una - ca, fan1) * s1;
+        const double g2 = harten_fix(una + ca, fan2) * s2;
+        double diss[NF];
+        diss[0] = g1 + g2;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const bool n = (k == nd);
+            double t = g1 * (n ? (una - ca) : ua[k]);
+            t = n ? t : (t + (fabs(una) * ((UR[1 + k] - UL[1 + k]) - (ua[k] * jh))));
+            diss[1 + k] = t + (g2 * (n ? (una + ca) : ua[k]));
+        }
+#pragma unroll
+        for (int q = 0; q < NF; ++q) Fh[q] = 0.5 * ((FL[q] + FR[q]) - diss[q]);
+        return;
+    }
+    const double SL = vmin(uL - wl.c, uR - wr.c);
+    const double SR = vmax(uL + wl.c, uR + wr.c);
+    const bool takeL = (SL >= 0.0);
+    const bool takeR = (SR <= 0.0);
+    const double den = SR - SL;
+    const double slsr = SL * SR;
+#pragma unroll
+    for (int q = 0; q < NF; ++q) {
+        const double mid = (((SR * FL[q]) - (SL * FR[q])) + (slsr * (UR[q] - UL[q]))) / den;
+        Fh[q] = takeL ? FL[q] : (takeR ? FR[q] : mid);
+    }
+}
+
 // ---------------------------------------------------------------- scalar equations
 
 template <int DIM, int EQ, int FLUX>
@@ -249,6 +349,8 @@ __device__ __forceinline__ void numflux(const double* UL, const double* UR, int 
 {
     if constexpr (EQ == EQ_EULER) {
         euler_numflux<DIM, FLUX>(UL, UR, nd, Fh, ph);
+    } else if constexpr (EQ == EQ_SWE) {
+        swe_numflux<DIM, FLUX>(UL, UR, nd, Fh, ph);
     } else {
         Fh[0] = scalar_numflux<DIM, EQ, FLUX>(UL[0], UR[0], nd, ph);
     }
@@ -331,6 +433,14 @@ __device__ __forceinline__ double cell_speed(const double* U, const Phys& ph, bo
     if constexpr (EQ == EQ_EULER) {
         const EulerPrim<DIM> w = euler_prim<DIM>(U, ph);
         b = b || !(U[0] > 0.0) || !(w.p > 0.0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const double a = (fabs(w.u[k]) + w.c) * ph.inv_dx[k];
+            m = (k == 0) ? a : vmax(m, a);
+        }
+    } else if constexpr (EQ == EQ_SWE) {
+        const SwePrim<DIM> w = swe_prim<DIM>(U, ph);
+        b = b || !(U[0] > 0.0);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const double a = (fabs(w.u[k]) + w.c) * ph.inv_dx[k];

@@ -23,7 +23,7 @@ struct CombineArgs {
     int32_t nq;
 };
 
-void launch_welford_diff(int nf, bool euler, const double* fine, const double* coarse,
+void launch_welford_diff(int nf, int kind, const double* fine, const double* coarse,
                          const DiffGeom& geo, int32_t batch, int64_t count0, double* mean,
                          double* m2, hipStream_t s);
 void launch_mlmc_combine(const CombineArgs& a, double* out, hipStream_t s);
@@ -31,7 +31,7 @@ void launch_mlmc_combine(const CombineArgs& a, double* out, hipStream_t s);
 // Workgroups per (sample, quantity) of the structure-function pass.
 int sf_blocks_per_field(int32_t dim, const int32_t n[3]);
 // qout (may be null): also write the quantity fields of the batch, [sample][quantity][cells].
-void launch_welford(int nf, bool euler, const double* state, int64_t cells, int32_t batch,
+void launch_welford(int nf, int kind, const double* state, int64_t cells, int32_t batch,
                     int64_t count0, double* mean, double* m2, double* qout, hipStream_t s);
 void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t nq, int32_t max_h,
                        int32_t batch, double* partial, hipStream_t s);

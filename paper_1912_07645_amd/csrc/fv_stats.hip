@@ -11,7 +11,9 @@ namespace fvk {
 // cell keeps the running moments of every quantity in registers. With qout, the quantity
 // fields of the samples are also written there ([sample][quantity][cells]) for the
 // structure functions, so the state is read once.
-template <int NF, bool EULER>
+// KIND: 0 the field itself; 1 Euler (the momenta divided by rho); 2 shallow water (the
+// momenta divided by h).
+template <int NF, int KIND>
 __global__ void __launch_bounds__(256)
 welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, int64_t count0,
                double* __restrict__ mean, double* __restrict__ m2, double* __restrict__ qout)
@@ -29,10 +31,10 @@ welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, i
         double x[NF];
 #pragma unroll
         for (int q = 0; q < NF; ++q) x[q] = U[q * cells];
-        if (EULER) {
+        if (KIND != 0) {
             const double ir = 1.0 / x[0];
 #pragma unroll
-            for (int q = 1; q < NF - 1; ++q) x[q] = x[q] * ir;
+            for (int q = 1; q < ((KIND == 1) ? NF - 1 : NF); ++q) x[q] = x[q] * ir;
         }
         if (qout) {
             double* Q = qout + (int64_t)b * NF * cells + c;
@@ -242,7 +244,7 @@ __global__ void sf_welford_kernel(const double* __restrict__ x, int32_t nq, int3
 
 // Multilevel Monte Carlo level differences: per fine cell, Welford over coupled samples of
 // x = q(u_fine) - q(u_coarse at the parent cell) (piecewise-constant prolongation).
-template <int NF, bool EULER>
+template <int NF, int KIND>
 __global__ void __launch_bounds__(256)
 welford_diff_kernel(const double* __restrict__ fine, const double* __restrict__ coarse,
                     DiffGeom geo, int32_t batch, int64_t count0, double* __restrict__ mean,
@@ -271,11 +273,11 @@ welford_diff_kernel(const double* __restrict__ fine, const double* __restrict__ 
             xf[q] = Uf[q * cells];
             xc[q] = Uc[q * ccells];
         }
-        if (EULER) {
+        if (KIND != 0) {
             const double irf = 1.0 / xf[0];
             const double irc = 1.0 / xc[0];
 #pragma unroll
-            for (int q = 1; q < NF - 1; ++q) {
+            for (int q = 1; q < ((KIND == 1) ? NF - 1 : NF); ++q) {
                 xf[q] = xf[q] * irf;
                 xc[q] = xc[q] * irc;
             }
@@ -320,18 +322,20 @@ __global__ void mlmc_combine_kernel(const CombineArgs a, double* __restrict__ ou
     }
 }
 
-void launch_welford_diff(int nf, bool euler, const double* fine, const double* coarse,
+void launch_welford_diff(int nf, int kind, const double* fine, const double* coarse,
                          const DiffGeom& geo, int32_t batch, int64_t count0, double* mean,
                          double* m2, hipStream_t s)
 {
     const int64_t cells = (int64_t)geo.nf[0] * geo.nf[1] * geo.nf[2];
     const unsigned nb = (unsigned)((cells + 255) / 256);
-#define FV_DIFF(NFV, E) hipLaunchKernelGGL((welford_diff_kernel<NFV, E>), dim3(nb), dim3(256), 0, s, \
+#define FV_DIFF(NFV, K) hipLaunchKernelGGL((welford_diff_kernel<NFV, K>), dim3(nb), dim3(256), 0, s, \
                                            fine, coarse, geo, batch, count0, mean, m2)
-    if (!euler) FV_DIFF(1, false);
-    else if (nf == 3) FV_DIFF(3, true);
-    else if (nf == 4) FV_DIFF(4, true);
-    else FV_DIFF(5, true);
+    if (kind == 0) FV_DIFF(1, 0);
+    else if (kind == 2 && nf == 2) FV_DIFF(2, 2);
+    else if (kind == 2) FV_DIFF(3, 2);
+    else if (nf == 3) FV_DIFF(3, 1);
+    else if (nf == 4) FV_DIFF(4, 1);
+    else FV_DIFF(5, 1);
 #undef FV_DIFF
 }
 
@@ -362,22 +366,24 @@ int sf_blocks_per_field(int32_t dim, const int32_t n[3])
     return (int)((g.items[dim] + per - 1) / per);
 }
 
-template <int NF, bool EULER>
+template <int NF, int KIND>
 static void welford_launch(const double* state, int64_t cells, int32_t batch, int64_t count0,
                            double* mean, double* m2, double* qout, hipStream_t s)
 {
     const unsigned nb = (unsigned)((cells + 255) / 256);
-    hipLaunchKernelGGL((welford_kernel<NF, EULER>), dim3(nb), dim3(256), 0, s, state, cells,
+    hipLaunchKernelGGL((welford_kernel<NF, KIND>), dim3(nb), dim3(256), 0, s, state, cells,
                        batch, count0, mean, m2, qout);
 }
 
-void launch_welford(int nf, bool euler, const double* state, int64_t cells, int32_t batch,
+void launch_welford(int nf, int kind, const double* state, int64_t cells, int32_t batch,
                     int64_t count0, double* mean, double* m2, double* qout, hipStream_t s)
 {
-    if (!euler) welford_launch<1, false>(state, cells, batch, count0, mean, m2, qout, s);
-    else if (nf == 3) welford_launch<3, true>(state, cells, batch, count0, mean, m2, qout, s);
-    else if (nf == 4) welford_launch<4, true>(state, cells, batch, count0, mean, m2, qout, s);
-    else welford_launch<5, true>(state, cells, batch, count0, mean, m2, qout, s);
+    if (kind == 0) welford_launch<1, 0>(state, cells, batch, count0, mean, m2, qout, s);
+    else if (kind == 2 && nf == 2) welford_launch<2, 2>(state, cells, batch, count0, mean, m2, qout, s);
+    else if (kind == 2) welford_launch<3, 2>(state, cells, batch, count0, mean, m2, qout, s);
+    else if (nf == 3) welford_launch<3, 1>(state, cells, batch, count0, mean, m2, qout, s);
+    else if (nf == 4) welford_launch<4, 1>(state, cells, batch, count0, mean, m2, qout, s);
+    else welford_launch<5, 1>(state, cells, batch, count0, mean, m2, qout, s);
 }
 
 void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t nq, int32_t max_h,

@@ -17,7 +17,7 @@ FV_OK, FV_EINVAL, FV_ENOTSUP, FV_ENOMEM, FV_EDEVICE, FV_ENONPHYS, FV_EMAXSTEPS, 
 STATUS_NAMES = {0: "FV_OK", 1: "FV_EINVAL", 2: "FV_ENOTSUP", 3: "FV_ENOMEM", 4: "FV_EDEVICE",
                 5: "FV_ENONPHYS", 6: "FV_EMAXSTEPS", 7: "FV_ECFL"}
 BC = {"periodic": 0, "transmissive": 1}
-EQ = {"advection": 0, "burgers": 1, "euler": 2}
+EQ = {"advection": 0, "burgers": 1, "euler": 2, "swe": 3}
 FLUX = {"rusanov": 0, "hll": 1, "hllc": 2, "roe": 3, "ec": 4}
 RECON = {"first_order": 0, "muscl_minmod": 1, "weno3": 2, "eno2": 3}
 INTEGRATOR = {"forward_euler": 0, "ssprk2": 1, "ssprk3": 2}
@@ -29,7 +29,8 @@ class fv_grid(C.Structure):
 
 
 class fv_equation(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("gamma", C.c_double), ("velocity", C.c_double * 3)]
+    _fields_ = [("kind", C.c_int32), ("gamma", C.c_double), ("velocity", C.c_double * 3),
+                ("gravity", C.c_double)]
 
 
 class FVError(RuntimeError):
@@ -124,10 +125,11 @@ def make_grid(dim, n, bc="periodic", lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> 
     return g
 
 
-def make_equation(kind="euler", gamma=1.4, velocity=(0.0, 0.0, 0.0)) -> fv_equation:
+def make_equation(kind="euler", gamma=1.4, velocity=(0.0, 0.0, 0.0), gravity=9.81) -> fv_equation:
     e = fv_equation()
     e.kind = EQ[kind] if isinstance(kind, str) else int(kind)
     e.gamma = float(gamma)
+    e.gravity = float(gravity)
     for k in range(3):
         e.velocity[k] = float(velocity[k]) if k < len(velocity) else 0.0
     return e

@@ -24,12 +24,12 @@ class Solver:
 
     def __init__(self, dim, n, eq="euler", flux="rusanov", recon="first_order",
                  integrator="forward_euler", bc="periodic", gamma=1.4, velocity=(0.0, 0.0, 0.0),
-                 lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), device=None):
+                 lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), device=None, gravity=9.81):
         self.device = torch.device(device if device is not None else "cuda")
         self.dim = dim
         self.n = tuple(list(n) + [1] * (3 - len(n)))
         self.grid = fv.make_grid(dim, n, bc, lo, hi)
-        self.eq = fv.make_equation(eq, gamma, velocity)
+        self.eq = fv.make_equation(eq, gamma, velocity, gravity)
         self.names = dict(eq=eq, flux=flux, recon=recon, integrator=integrator)
         with torch.cuda.device(self.device):
             self.handle = fv.fv_create(self.grid, self.eq, fv.FLUX[flux], fv.RECON[recon],
@@ -88,7 +88,7 @@ class Solver:
 
     @property
     def num_quantities(self) -> int:
-        return self.nf if self.names["eq"] == "euler" else 1
+        return self.nf if self.names["eq"] in ("euler", "swe") else 1
 
     def point_pdf(self, U, quantity, points, lo, hi, nbins, counts=None):
         """Histograms over the samples of U of `quantity` at each cell of `points` (flat cell

@@ -22,7 +22,7 @@ def solver_for(p: O.Problem, variant=None):
     from paper_1912_07645_amd import Solver
     s = Solver(dim=p.dim, n=p.n[:p.dim], eq=p.eq, flux=p.flux, recon=p.recon,
                integrator=p.integrator, bc=p.bc[:3], gamma=p.gamma, velocity=p.vel,
-               lo=p.lo, hi=p.hi)
+               lo=p.lo, hi=p.hi, gravity=p.gravity)
     if variant is not None:
         s.set_variant(variant)
     return s

@@ -1,0 +1,109 @@
+"""GPU parity of the shallow-water equations against the oracle, bit for bit: every
+reconstruction with the Rusanov, HLL and Roe fluxes and every stepper in 1D and 2D on ragged
+grids, the dam break to its final time, the circular dam break, a non-physical depth, and the
+statistics (mean, variance, structure functions, PDFs) of shallow-water samples."""
+import numpy as np
+import pytest
+
+import fv_inputs as fi
+import oracle as O
+from gpu_helpers import assert_parity, gpu_evolve, note, solver_for, torch_gpu
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {1: (600,), 2: (150, 20)}
+COMBOS = [(d, fl, rc, it) for d in (1, 2) for fl in ("rusanov", "hll", "roe")
+          for rc in ("first_order", "muscl_minmod", "weno3", "eno2")
+          for it in ("forward_euler", "ssprk2", "ssprk3")]
+
+
+@pytest.mark.parametrize("dim,flux,recon,integ", COMBOS)
+def test_swe_schemes_match_oracle(dim, flux, recon, integ):
+    idx = COMBOS.index((dim, flux, recon, integ))
+    bc = ("transmissive",) * 3 if idx % 2 == 0 else ("periodic",) * 3
+    p = O.Problem(dim=dim, n=SHAPES[dim], eq="swe", flux=flux, recon=recon, integrator=integ,
+                  bc=bc, gravity=9.81)
+    U0 = fi.random_smooth_swe(40 + idx, p.state_shape[1:], dim, batch=2)
+    note("swe", dim, flux, recon, integ, bc[0])
+    R, rt, rs, re = O.evolve(p, U0, 1e3, 0.4, max_steps=6)
+    G, gt, gs, ge, st = gpu_evolve(p, U0, 1e3, 0.4, max_steps=6, mode="advance")
+    assert np.all(gs == 6) and np.array_equal(gt, rt)
+    assert_parity(G, R, what=f"swe {dim}D {flux} {recon} {integ}")
+
+
+def test_dam_break_to_final_time():
+    N = 1024
+    p = O.Problem(dim=1, n=(N,), eq="swe", flux="roe", recon="eno2", integrator="ssprk2",
+                  bc=("transmissive",), gravity=9.81)
+    U0 = fi.swe_dam_break_1d(N)
+    note("swe dam break")
+    R, rt, rs, re = O.evolve(p, U0, 0.05, 0.45)
+    G, gt, gs, ge, st = gpu_evolve(p, U0, 0.05, 0.45)
+    assert gs[0] == rs[0] and gt[0] == rt[0] == 0.05 and ge[0] == 0
+    assert_parity(G, R, what="swe dam break")
+
+
+@pytest.mark.parametrize("flux", ["hll", "roe"])
+def test_circular_dam_break(flux):
+    n = 256
+    p = O.Problem(dim=2, n=(n, n), eq="swe", flux=flux, recon="weno3", integrator="ssprk3",
+                  gravity=9.81)
+    U0 = fi.swe_circular_dam_break(n, batch=2)
+    U0[1, 0] *= 1.5
+    note("swe circular", flux)
+    R, rt, rs, re = O.evolve(p, U0, 1.0, 0.4, max_steps=20)
+    G, gt, gs, ge, st = gpu_evolve(p, U0, 1.0, 0.4, max_steps=20, mode="advance")
+    assert np.all(gs == 20) and np.array_equal(gt, rt)
+    assert_parity(G, R, what=f"swe circular {flux}")
+
+
+def test_negative_depth_is_non_physical():
+    p = O.Problem(dim=1, n=(64,), eq="swe", flux="hll", bc=("transmissive",), gravity=9.81)
+    U0 = fi.swe_dam_break_1d(64)
+    U0 = np.concatenate([U0, U0])
+    U0[1, 0, 0, 0, 10] = -0.5
+    R, rt, rs, re = O.evolve(p, U0, 0.05, 0.45)
+    G, gt, gs, ge, st = gpu_evolve(p, U0, 0.05, 0.45)
+    assert re[1] == 5 and ge[1] == 5 and ge[0] == 0
+    assert np.array_equal(gs, rs) and np.array_equal(gt, rt)
+    assert_parity(G[:1], R[:1], what="swe sample 0")
+
+
+def test_swe_statistics_match_oracle():
+    torch = torch_gpu()
+    from paper_1912_07645_amd import Stats
+    n = 48
+    p = O.Problem(dim=2, n=(n, n), eq="swe", flux="hll", recon="muscl_minmod",
+                  integrator="ssprk2", gravity=9.81)
+    U0 = fi.random_smooth_swe(77, (1, n, n), 2, batch=12)
+    G, *_ = gpu_evolve(p, U0, 1e3, 0.4, max_steps=5, mode="advance")
+    s = solver_for(p)
+    st = Stats(s, max_h=6)
+    Ud = torch.from_numpy(G).to("cuda")
+    st.accumulate(Ud)
+    res = st.read()
+    R = O.Stats(p, max_h=6)
+    R.accumulate(G)
+    assert res["count"] == 12
+    assert np.array_equal(res["mean"].cpu().numpy(), R.mean)
+    assert np.array_equal(res["var"].cpu().numpy(), R.variance())
+    assert np.allclose(res["s2_mean"].cpu().numpy(), R.s2(), rtol=1e-12, atol=0)
+    pts = [0, 7, n * n - 1]
+    for q, (lo, hi) in enumerate([(0.8, 1.2), (-0.4, 0.4), (-0.4, 0.4)]):
+        Gp = s.point_pdf(Ud, q, pts, lo, hi, 9).cpu().numpy()
+        assert np.array_equal(Gp, O.point_pdf(p, G, q, pts, lo, hi, 9))
+    S = s.structure_shell(Ud, 4, 2, True).cpu().numpy()
+    Rs = O.structure_shell_batch(p, G, 4, 2, True)
+    assert (np.abs(S - Rs) <= 1e-12 * np.abs(Rs)).all()
+
+
+def test_swe_rejections():
+    import paper_1912_07645_amd.fv as fv
+    from paper_1912_07645_amd import Solver
+    for kw, want in [(dict(dim=3, n=(8, 8, 8), flux="rusanov"), fv.FV_ENOTSUP),
+                     (dict(dim=1, n=(8,), flux="hllc"), fv.FV_ENOTSUP),
+                     (dict(dim=1, n=(8,), flux="ec"), fv.FV_ENOTSUP),
+                     (dict(dim=1, n=(8,), flux="hll", gravity=0.0), fv.FV_EINVAL)]:
+        with pytest.raises(fv.FVError) as e:
+            Solver(eq="swe", **kw)
+        assert e.value.status == want
