@@ -11,7 +11,7 @@ state already resident in HBM), the roofline of the dominant kernel (the stage k
 timed with HIP events on the library's stream over its own launches) and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh3d|mc|sod]
+    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh3d|mc|sod|swe2d]
     python bench.py --copy-calibration     # plain copy of known size, for rocprof counters
 """
 from __future__ import annotations
@@ -77,6 +77,9 @@ WORKLOADS = {
     "kh2d_roe": dict(name="kh2d_1024x1024_weno3_roe_ssprk3", dim=2, n=1024, flux="roe",
                      recon="weno3", integrator="ssprk3", cfl=0.4, batch=1, seed=1912,
                      steps=1000, warmup=50, cpu_steps=4),
+    "swe2d": dict(name="swe_circular_dam_break_1024x1024_muscl_hll_ssprk2", eq="swe", dim=2,
+                  n=1024, flux="hll", recon="muscl_minmod", integrator="ssprk2", cfl=0.4,
+                  batch=1, seed=0, steps=2000, warmup=100, cpu_steps=8),
     "mc": dict(name="kh2d_256x256_x1024_samples_weno3_hllc_ssprk3", dim=2, n=256, flux="hllc",
                recon="weno3", integrator="ssprk3", cfl=0.4, batch=1024, seed=1912,
                steps=50, warmup=5, cpu_steps=2),
@@ -101,6 +104,8 @@ PROFILE_SUMMARY = {"kh2d": "stage_kernel_kh2d_1024.md", "kh3d": "stage_kernel_kh
 def initial_state(w):
     import numpy as np
     import fv_inputs as fi
+    if w.get("eq") == "swe":
+        return fi.swe_circular_dam_break(w["n"], batch=w["batch"])
     if w["dim"] == 1:
         return fi.sod_state(w["n"])
     if w["dim"] == 2:
@@ -144,7 +149,7 @@ def cpu_baseline(w, U0, steps):
     """The oracle as it stands, on the host's cores, over a bounded prefix of the run."""
     import oracle as O
     cores = O.set_threads(0)
-    p = O.Problem(dim=w["dim"], n=(w["n"],) * w["dim"], eq="euler", flux=w["flux"],
+    p = O.Problem(dim=w["dim"], n=(w["n"],) * w["dim"], eq=w.get("eq", "euler"), flux=w["flux"],
                   recon=w["recon"], integrator=w["integrator"],
                   bc=("transmissive",) if w["dim"] == 1 else ("periodic",) * 3)
     samples = min(U0.shape[0], 2)
@@ -385,7 +390,7 @@ def measure(a, w, steps=None, warmup=None):
     dev = torch.device("cuda:0")
     U0 = initial_state(w)
     bc = "transmissive" if w["dim"] == 1 else "periodic"
-    s = Solver(dim=w["dim"], n=(w["n"],) * w["dim"], eq="euler", flux=w["flux"],
+    s = Solver(dim=w["dim"], n=(w["n"],) * w["dim"], eq=w.get("eq", "euler"), flux=w["flux"],
                recon=w["recon"], integrator=w["integrator"], bc=bc, device=dev)
     U = torch.from_numpy(U0).to(dev)
     B = U.shape[0]
@@ -432,7 +437,7 @@ def measure(a, w, steps=None, warmup=None):
     # bounds the stage kernel's own duration from above.
     nstages = {"forward_euler": 1, "ssprk2": 2, "ssprk3": 3}[w["integrator"]]
     launches = K * nstages
-    nf = w["dim"] + 2
+    nf = s.nf
     bytes_step = algorithmic_bytes_per_cell_step(nf, w["integrator"]) * cells * B
     avg_launch_s = ev0.elapsed_time(ev1) * 1e-3 / launches
     bytes_per_launch = bytes_step / nstages
@@ -440,7 +445,7 @@ def measure(a, w, steps=None, warmup=None):
     hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_per_launch,
            "traffic": measured_traffic(a.workload)}
-    if w["recon"] == "weno3" and w["flux"] in ("hllc", "roe"):
+    if w.get("eq", "euler") == "euler" and w["recon"] == "weno3" and w["flux"] in ("hllc", "roe"):
         ops_launch = lane_ops_per_cell_stage(w["dim"], w["integrator"], w["flux"]) * cells * B
         alu_tops = ops_launch / avg_launch_s / 1e12
         roof = {"bound": "alu", "achieved": alu_tops, "peak": FP64_LANE_OPS_PEAK / 1e12,
