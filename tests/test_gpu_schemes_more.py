@@ -79,3 +79,16 @@ def test_ec_rejected_for_euler_and_advection():
         with pytest.raises(fv.FVError) as e:
             Solver(dim=1, n=(16,), eq=eq, flux="ec")
         assert e.value.status == fv.FV_ENOTSUP
+
+
+def test_kh_roe_1024_full_size_bitwise():
+    """The WENO3 + Roe benchmark configuration at its full 1024^2 size, 3 steps, every cell."""
+    c, phi = fi.kh_coefficients(1912, [0])
+    U0 = fi.kh2d_state(1024, c, phi)
+    p = O.Problem(dim=2, n=(1024, 1024), eq="euler", flux="roe", recon="weno3", integrator="ssprk3")
+    note("kh roe 1024 oracle")
+    R, rt, rs, re = O.evolve(p, U0, 2.0, 0.4, max_steps=3)
+    note("kh roe 1024 gpu")
+    G, gt, gs, ge, st = gpu_evolve(p, U0, 2.0, 0.4, max_steps=3, mode="advance")
+    assert gs[0] == 3 and gt[0] == rt[0]
+    assert_parity(G, R, what="kh roe 1024")

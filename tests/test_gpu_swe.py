@@ -124,3 +124,18 @@ def test_swe_every_tile_variant():
             G, gt, gs, ge, st = gpu_evolve(p, U0, 1e3, 0.4, max_steps=7, mode="advance", variant=v)
             assert np.all(gs == 7) and np.array_equal(gt, rt)
             assert_parity(G, R, what=f"swe variant {v} {bc}")
+
+
+def test_swe_circular_dam_break_1024_full_size_bitwise():
+    """The shallow-water benchmark configuration (1024^2, MUSCL + HLL + SSP-RK2) at full size,
+    5 steps, every cell."""
+    n = 1024
+    p = O.Problem(dim=2, n=(n, n), eq="swe", flux="hll", recon="muscl_minmod", integrator="ssprk2",
+                  gravity=9.81)
+    U0 = fi.swe_circular_dam_break(n)
+    note("swe 1024 oracle")
+    R, rt, rs, re = O.evolve(p, U0, 1.0, 0.4, max_steps=5)
+    note("swe 1024 gpu")
+    G, gt, gs, ge, st = gpu_evolve(p, U0, 1.0, 0.4, max_steps=5, mode="advance")
+    assert gs[0] == 5 and gt[0] == rt[0]
+    assert_parity(G, R, what="swe 1024")
