@@ -45,6 +45,10 @@
  *   - the Roe flux (Section 2.1 names it) uses Roe's average state and Harten's entropy fix
  *     on the acoustic waves (roe_euler); for Burgers the Roe speed is (uL + uR) / 2 with the
  *     fix over the rarefaction fan, for advection the velocity (plain upwinding);
+ *   - Godunov's flux (Section 2.1) is the flux of the exact Riemann solution at x/t = 0, for
+ *     the Euler equations by Toro's pressure-function Newton iteration (a fixed 20 steps from
+ *     the primitive-variable guess) and wave sampling (godunov_euler); it calls pow(), which
+ *     the device library need not round like this one, so the GPU agrees to rounding only;
  *   - the high-order entropy-conservative fluxes Section 2.1 names are taken, for Burgers, as
  *     Tadmor's two-point flux (uL^2 + uL uR + uR^2) / 6;
  *   - ENO (Section 2.1) is the second-order ENO reconstruction: the one-sided difference of
@@ -62,7 +66,8 @@
 /* ---------------------------------------------------------------- problem description */
 
 enum { OC_EQ_ADVECTION = 0, OC_EQ_BURGERS = 1, OC_EQ_EULER = 2, OC_EQ_SWE = 3 };
-enum { OC_FLUX_RUSANOV = 0, OC_FLUX_HLL = 1, OC_FLUX_HLLC = 2, OC_FLUX_ROE = 3, OC_FLUX_EC = 4 };
+enum { OC_FLUX_RUSANOV = 0, OC_FLUX_HLL = 1, OC_FLUX_HLLC = 2, OC_FLUX_ROE = 3, OC_FLUX_EC = 4,
+       OC_FLUX_GODUNOV = 5 };
 enum { OC_REC_FIRST = 0, OC_REC_MUSCL = 1, OC_REC_WENO3 = 2, OC_REC_ENO2 = 3 };
 enum { OC_INT_FE = 0, OC_INT_RK2 = 1, OC_INT_RK3 = 2 };
 enum { OC_BC_PERIODIC = 0, OC_BC_TRANSMISSIVE = 1 };
@@ -116,7 +121,7 @@ int oc_validate(const oc_problem* P)
         if (P->bc[k] != OC_BC_PERIODIC && P->bc[k] != OC_BC_TRANSMISSIVE) return OC_EINVAL;
     }
     if (P->eq < 0 || P->eq > 3) return OC_EINVAL;
-    if (P->flux < 0 || P->flux > 4) return OC_EINVAL;
+    if (P->flux < 0 || P->flux > 5) return OC_EINVAL;
     if (P->recon < 0 || P->recon > 3) return OC_EINVAL;
     if (P->integrator < 0 || P->integrator > 2) return OC_EINVAL;
     if (P->flux == OC_FLUX_HLLC && P->eq != OC_EQ_EULER) return OC_ENOTSUP;
@@ -125,6 +130,7 @@ int oc_validate(const oc_problem* P)
     if (P->eq == OC_EQ_SWE) {
         if (!(P->grav > 0.0)) return OC_EINVAL;
         if (P->dim > 2) return OC_ENOTSUP;
+        if (P->flux == OC_FLUX_GODUNOV) return OC_ENOTSUP;
     }
     return OC_OK;
 }
@@ -183,6 +189,82 @@ static double harten(double l, double d)
 {
     const double al = fabs(l);
     return (al >= d) ? al : (((l * l) + (d * d)) / (2.0 * d));
+}
+
+/* Toro's pressure function f_K(p) of side K and its derivative: a shock for p > p_K,
+ * a rarefaction otherwise. */
+static void toro_fk(double p, double rK, double pK, double cK, double g, double* f, double* df)
+{
+    if (p > pK) {
+        const double A = 2.0 / ((g + 1.0) * rK);
+        const double B = ((g - 1.0) / (g + 1.0)) * pK;
+        const double q = sqrt(A / (p + B));
+        *f = (p - pK) * q;
+        *df = q * (1.0 - (0.5 * ((p - pK) / (B + p))));
+    } else {
+        const double pr = p / pK;
+        *f = ((2.0 * cK) / (g - 1.0)) * (pow(pr, (g - 1.0) / (2.0 * g)) - 1.0);
+        *df = (1.0 / (rK * cK)) * pow(pr, -((g + 1.0) / (2.0 * g)));
+    }
+}
+
+/* Godunov's flux for the Euler equations: the physical flux of the exact Riemann solution at
+ * x/t = 0 (Toro, ch. 4). The star pressure solves f_L(p) + f_R(p) + (u_R - u_L) = 0 by 20
+ * Newton steps from the primitive-variable guess, p kept at or above 1e-12 (p_L + p_R); the
+ * state at x/t = 0 is sampled from the waves; tangential velocities are those of the side of
+ * the contact. */
+static void godunov_euler(const double* UL, const double* UR, const oc_prim* wl,
+                          const oc_prim* wr, int dim, int nd, double g, double* Fh)
+{
+    const double rL = UL[0], rR = UR[0];
+    const double uL = wl->u[nd], uR = wr->u[nd];
+    const double pL = wl->p, pR = wr->p, cL = wl->c, cR = wr->c;
+    const double floor_p = 1e-12 * (pL + pR);
+    double p = (0.5 * (pL + pR)) - (0.125 * (((uR - uL) * (rL + rR)) * (cL + cR)));
+    p = dmax(floor_p, p);
+    double fL, dfL, fR, dfR;
+    for (int it = 0; it < 20; ++it) {
+        toro_fk(p, rL, pL, cL, g, &fL, &dfL);
+        toro_fk(p, rR, pR, cR, g, &fR, &dfR);
+        p = dmax(floor_p, p - (((fL + fR) + (uR - uL)) / (dfL + dfR)));
+    }
+    toro_fk(p, rL, pL, cL, g, &fL, &dfL);
+    toro_fk(p, rR, pR, cR, g, &fR, &dfR);
+    const double um = (0.5 * (uL + uR)) + (0.5 * (fR - fL));
+    const double g1 = (g - 1.0) / (2.0 * g), g6 = (g - 1.0) / (g + 1.0);
+    double rho, un, pr;
+    const int left = (um >= 0.0);
+    /* side K and its sign: the right side is the left side mirrored (u -> -u) */
+    const double sg = left ? 1.0 : -1.0;
+    const double rK = left ? rL : rR, pK = left ? pL : pR, cK = left ? cL : cR;
+    const double uK = sg * (left ? uL : uR), umK = sg * um;
+    if (p > pK) {
+        const double SK = uK - (cK * sqrt((((g + 1.0) / (2.0 * g)) * (p / pK)) + g1));
+        if (SK >= 0.0) { rho = rK; un = uK; pr = pK; }
+        else { rho = rK * (((p / pK) + g6) / ((g6 * (p / pK)) + 1.0)); un = umK; pr = p; }
+    } else if (uK - cK >= 0.0) {
+        rho = rK; un = uK; pr = pK;
+    } else {
+        const double cm = cK * pow(p / pK, g1);
+        if (umK - cm < 0.0) {
+            rho = rK * pow(p / pK, 1.0 / g); un = umK; pr = p;
+        } else {
+            const double c = (2.0 / (g + 1.0)) * (cK + (((g - 1.0) / 2.0) * uK));
+            un = c;
+            rho = rK * pow(c / cK, 2.0 / (g - 1.0));
+            pr = pK * pow(c / cK, (2.0 * g) / (g - 1.0));
+        }
+    }
+    un = sg * un;
+    const oc_prim* wt = left ? wl : wr;
+    double u[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < dim; ++k) u[k] = (k == nd) ? un : wt->u[k];
+    double ke = rho * (u[0] * u[0]);
+    for (int k = 1; k < dim; ++k) ke = ke + (rho * (u[k] * u[k]));
+    const double E = (pr / (g - 1.0)) + (0.5 * ke);
+    Fh[0] = rho * un;
+    for (int k = 0; k < dim; ++k) Fh[1 + k] = ((rho * u[k]) * un) + ((k == nd) ? pr : 0.0);
+    Fh[dim + 1] = (E + pr) * un;
 }
 
 /* Roe's flux for the Euler equations: F = (F_L + F_R)/2 - (1/2) sum_i |l_i| alpha_i K_i over
@@ -351,6 +433,10 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
             roe_euler(UL, UR, &wl, &wr, FL, FR, dim, nd, gm1, Fh);
             return;
         }
+        if (P->flux == OC_FLUX_GODUNOV) {
+            godunov_euler(UL, UR, &wl, &wr, dim, nd, gamma, Fh);
+            return;
+        }
         double SL = dmin(uL - wl.c, uR - wr.c);
         double SR = dmax(uL + wl.c, uR + wr.c);
         if (SL >= 0.0) { for (int q = 0; q < nf; ++q) Fh[q] = FL[q]; return; }
@@ -414,6 +500,20 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
             d = 0.0;
         }
         Fh[0] = 0.5 * ((FL + FR) - (harten(a, d) * (uR - uL)));
+        return;
+    }
+    if (P->flux == OC_FLUX_GODUNOV) {
+        /* the exact Riemann solution at x/t = 0: for Burgers the shock speed (uL + uR)/2 picks
+         * the side, a transonic rarefaction gives f(0) = 0; advection is upwinding */
+        if (P->eq == OC_EQ_BURGERS) {
+            if (uL > uR) {
+                Fh[0] = ((0.5 * (uL + uR)) >= 0.0) ? FL : FR;
+            } else {
+                Fh[0] = (uL >= 0.0) ? FL : ((uR <= 0.0) ? FR : 0.0);
+            }
+        } else {
+            Fh[0] = (P->vel[nd] >= 0.0) ? FL : FR;
+        }
         return;
     }
     if (P->flux == OC_FLUX_EC) {
