@@ -11,7 +11,7 @@ state already resident in HBM), the roofline of the dominant kernel (the stage k
 timed with HIP events on the library's stream over its own launches) and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh3d|mc|sod|swe2d]
+    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh3d|mc|sod|swe2d]
     python bench.py --copy-calibration     # plain copy of known size, for rocprof counters
 """
 from __future__ import annotations
@@ -77,6 +77,9 @@ WORKLOADS = {
     "kh2d_roe": dict(name="kh2d_1024x1024_weno3_roe_ssprk3", dim=2, n=1024, flux="roe",
                      recon="weno3", integrator="ssprk3", cfl=0.4, batch=1, seed=1912,
                      steps=1000, warmup=50, cpu_steps=4),
+    "kh2d_godunov": dict(name="kh2d_1024x1024_weno3_godunov_ssprk3", dim=2, n=1024,
+                         flux="godunov", recon="weno3", integrator="ssprk3", cfl=0.4, batch=1,
+                         seed=1912, steps=200, warmup=20, cpu_steps=1),
     "swe2d": dict(name="swe_circular_dam_break_1024x1024_muscl_hll_ssprk2", eq="swe", dim=2,
                   n=1024, flux="hll", recon="muscl_minmod", integrator="ssprk2", cfl=0.4,
                   batch=1, seed=0, steps=2000, warmup=100, cpu_steps=8),

@@ -8,7 +8,7 @@
 namespace fvk {
 
 enum { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2, EQ_SWE = 3 };
-enum { FLUX_RUSANOV = 0, FLUX_HLL = 1, FLUX_HLLC = 2, FLUX_ROE = 3, FLUX_EC = 4 };
+enum { FLUX_RUSANOV = 0, FLUX_HLL = 1, FLUX_HLLC = 2, FLUX_ROE = 3, FLUX_EC = 4, FLUX_GODUNOV = 5 };
 enum { REC_FIRST = 0, REC_MUSCL = 1, REC_WENO3 = 2, REC_ENO2 = 3 };
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
 

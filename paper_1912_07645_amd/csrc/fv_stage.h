@@ -283,8 +283,14 @@ __device__ __forceinline__ int find_group(const Group* g, int ngroups, int64_t b
     return gi;
 }
 
+// Fewest waves per SIMD the register allocation must leave room for: 6 for the LDS-held tile
+// plans; the Euler Godunov flux (a Newton iteration with logarithms and exponentials) needs
+// 116-148 registers and would spill under the 80 that 6 waves leave, so it is allowed 2.
+template <int EQ, int FLUX, int HOLD>
+constexpr int stage_min_waves() { return (FLUX == FLUX_GODUNOV && EQ == EQ_EULER) ? 2 : (HOLD ? 6 : 1); }
+
 template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(HOLD ? 6 : 1, 8)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stage_min_waves<EQ, FLUX, HOLD>(), 8)))
 stage_kernel(const StageArgs args)
 {
     using T = StageTile<DIM, EQ, RECON, BX, BY, BZ, NT>;
