@@ -23,7 +23,7 @@ _BUILD = os.path.join(_HERE, "_build")
 _SO = os.path.join(_BUILD, "liboracle.so")
 
 EQ = {"advection": 0, "burgers": 1, "euler": 2, "swe": 3}
-FLUX = {"rusanov": 0, "hll": 1, "hllc": 2, "roe": 3, "ec": 4, "godunov": 5}
+FLUX = {"rusanov": 0, "hll": 1, "hllc": 2, "roe": 3, "ec": 4, "godunov": 5, "ec4": 6}
 RECON = {"first_order": 0, "muscl_minmod": 1, "weno3": 2, "eno2": 3}
 INTEGRATOR = {"forward_euler": 0, "ssprk2": 1, "ssprk3": 2}
 BC = {"periodic": 0, "transmissive": 1}

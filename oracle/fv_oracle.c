@@ -49,8 +49,12 @@
  *     the Euler equations by Toro's pressure-function Newton iteration (a fixed 20 steps from
  *     the primitive-variable guess) and wave sampling (godunov_euler); it calls pow(), which
  *     the device library need not round like this one, so the GPU agrees to rounding only;
- *   - the high-order entropy-conservative fluxes Section 2.1 names are taken, for Burgers, as
- *     Tadmor's two-point flux (uL^2 + uL uR + uR^2) / 6;
+ *   - the entropy-conservative fluxes Section 2.1 names: the two-point fluxes are Tadmor's
+ *     (uL^2 + uL uR + uR^2) / 6 for Burgers and Chandrashekar's (logarithmic means of rho and
+ *     rho / (2p)) for Euler (ec_euler); the fourth-order flux is LeFloch--Mercier--Rohde's
+ *     combination of the two-point flux over the cells i-1..i+2 (ec4_face), on the cell
+ *     values without reconstruction. The Euler flux calls log1p(), which the device library
+ *     need not round like this one;
  *   - ENO (Section 2.1) is the second-order ENO reconstruction: the one-sided difference of
  *     smaller magnitude, the left one on a tie.
  */
@@ -67,7 +71,7 @@
 
 enum { OC_EQ_ADVECTION = 0, OC_EQ_BURGERS = 1, OC_EQ_EULER = 2, OC_EQ_SWE = 3 };
 enum { OC_FLUX_RUSANOV = 0, OC_FLUX_HLL = 1, OC_FLUX_HLLC = 2, OC_FLUX_ROE = 3, OC_FLUX_EC = 4,
-       OC_FLUX_GODUNOV = 5 };
+       OC_FLUX_GODUNOV = 5, OC_FLUX_EC4 = 6 };
 enum { OC_REC_FIRST = 0, OC_REC_MUSCL = 1, OC_REC_WENO3 = 2, OC_REC_ENO2 = 3 };
 enum { OC_INT_FE = 0, OC_INT_RK2 = 1, OC_INT_RK3 = 2 };
 enum { OC_BC_PERIODIC = 0, OC_BC_TRANSMISSIVE = 1 };
@@ -121,11 +125,13 @@ int oc_validate(const oc_problem* P)
         if (P->bc[k] != OC_BC_PERIODIC && P->bc[k] != OC_BC_TRANSMISSIVE) return OC_EINVAL;
     }
     if (P->eq < 0 || P->eq > 3) return OC_EINVAL;
-    if (P->flux < 0 || P->flux > 5) return OC_EINVAL;
+    if (P->flux < 0 || P->flux > 6) return OC_EINVAL;
     if (P->recon < 0 || P->recon > 3) return OC_EINVAL;
     if (P->integrator < 0 || P->integrator > 2) return OC_EINVAL;
     if (P->flux == OC_FLUX_HLLC && P->eq != OC_EQ_EULER) return OC_ENOTSUP;
-    if (P->flux == OC_FLUX_EC && P->eq != OC_EQ_BURGERS) return OC_ENOTSUP;
+    if ((P->flux == OC_FLUX_EC || P->flux == OC_FLUX_EC4) &&
+        P->eq != OC_EQ_BURGERS && P->eq != OC_EQ_EULER) return OC_ENOTSUP;
+    if (P->flux == OC_FLUX_EC4 && P->recon != OC_REC_FIRST) return OC_ENOTSUP;
     if (P->eq == OC_EQ_EULER && !(P->gamma > 1.0)) return OC_EINVAL;
     if (P->eq == OC_EQ_SWE) {
         if (!(P->grav > 0.0)) return OC_EINVAL;
@@ -265,6 +271,50 @@ static void godunov_euler(const double* UL, const double* UR, const oc_prim* wl,
     Fh[0] = rho * un;
     for (int k = 0; k < dim; ++k) Fh[1 + k] = ((rho * u[k]) * un) + ((k == nd) ? pr : 0.0);
     Fh[dim + 1] = (E + pr) * un;
+}
+
+/* Logarithmic mean (a - b) / (ln a - ln b) of a, b > 0 (= a when a = b). With
+ * f = (a - b) / (a + b) it equals ((a + b) / 2) f / atanh(f); for f^2 < 1e-4 the series
+ * f / atanh(f) = 1 / (1 + f^2/3 + f^4/5 + f^6/7 + ...) is summed to the f^6 term (the rest is
+ * below 1.2e-17 relative). Otherwise ln a - ln b = log1p((a - b) / b), whose argument carries
+ * no cancellation. */
+static double logmean(double a, double b)
+{
+    const double f = (a - b) / (a + b);
+    const double u = f * f;
+    if (u < 1e-4) {
+        const double s = 1.0 + (u * ((1.0 / 3.0) + (u * ((1.0 / 5.0) + (u * (1.0 / 7.0))))));
+        return (0.5 * (a + b)) / s;
+    }
+    return (a - b) / log1p((a - b) / b);
+}
+
+/* Chandrashekar's entropy-conservative (and kinetic-energy-preserving) two-point flux for
+ * the Euler equations, entropy -rho s / (gamma - 1): with beta = rho / (2 p), logarithmic
+ * means rho^ and beta^, arithmetic means of u_k, rho and beta, and the mean of |u|^2,
+ *   F_rho = rho^ u_n, F_m_k = u_k F_rho + p~ delta_kn with p~ = mean(rho) / (2 mean(beta)),
+ *   F_E = (1 / (2 (gamma - 1) beta^) - mean(|u|^2) / 2) F_rho + sum_k mean(u_k) F_m_k. */
+static void ec_euler(const double* UL, const double* UR, const oc_prim* wl, const oc_prim* wr,
+                     int dim, int nd, double gm1, double* Fh)
+{
+    const double bL = UL[0] / (2.0 * wl->p), bR = UR[0] / (2.0 * wr->p);
+    const double rho_ln = logmean(UL[0], UR[0]);
+    const double beta_ln = logmean(bL, bR);
+    double um[3] = {0.0, 0.0, 0.0}, qL = 0.0, qR = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        um[k] = 0.5 * (wl->u[k] + wr->u[k]);
+        qL = qL + (wl->u[k] * wl->u[k]);
+        qR = qR + (wr->u[k] * wr->u[k]);
+    }
+    const double pt = (0.5 * (UL[0] + UR[0])) / (bL + bR);
+    const double Fr = rho_ln * um[nd];
+    Fh[0] = Fr;
+    double Fe = ((1.0 / ((2.0 * gm1) * beta_ln)) - (0.25 * (qL + qR))) * Fr;
+    for (int k = 0; k < dim; ++k) {
+        Fh[1 + k] = (um[k] * Fr) + ((k == nd) ? pt : 0.0);
+        Fe = Fe + (um[k] * Fh[1 + k]);
+    }
+    Fh[dim + 1] = Fe;
 }
 
 /* Roe's flux for the Euler equations: F = (F_L + F_R)/2 - (1/2) sum_i |l_i| alpha_i K_i over
@@ -437,6 +487,10 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
             godunov_euler(UL, UR, &wl, &wr, dim, nd, gamma, Fh);
             return;
         }
+        if (P->flux == OC_FLUX_EC || P->flux == OC_FLUX_EC4) {
+            ec_euler(UL, UR, &wl, &wr, dim, nd, gm1, Fh);
+            return;
+        }
         double SL = dmin(uL - wl.c, uR - wr.c);
         double SR = dmax(uL + wl.c, uR + wr.c);
         if (SL >= 0.0) { for (int q = 0; q < nf; ++q) Fh[q] = FL[q]; return; }
@@ -516,7 +570,7 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
         }
         return;
     }
-    if (P->flux == OC_FLUX_EC) {
+    if (P->flux == OC_FLUX_EC || P->flux == OC_FLUX_EC4) {
         /* Tadmor's entropy-conservative flux for Burgers (entropy u^2 / 2) */
         Fh[0] = (((uL * uL) + (uL * uR)) + (uR * uR)) / 6.0;
         return;
@@ -637,6 +691,31 @@ static void ghost_fill(const oc_problem* P, const oc_pad* pd, const double* U, d
 }
 
 /* L(U) = -sum_k (F_{i+1/2 e_k} - F_{i-1/2 e_k}) / dx_k for one sample (eq. 2.1). */
+/* Fourth-order entropy-conservative flux of LeFloch, Mercier and Rohde at the face between
+ * cells i = cL and i + 1 of the padded array W: the combination
+ *   F = sum_{r=1,2} alpha_r sum_{s=0}^{r-1} F~(U_{i-s}, U_{i-s+r}),  alpha = (4/3, -1/6),
+ * of the two-point entropy-conservative flux F~, i.e.
+ *   F = (4/3) F~(U_i, U_{i+1}) - (1/6) (F~(U_i, U_{i+2}) + F~(U_{i-1}, U_{i+1})).
+ * It acts on the cell values themselves (no reconstruction). */
+static void ec4_face(const oc_problem* P, int d, const double* W, int64_t PN, int64_t cL,
+                     int64_t stride, double* F)
+{
+    const int nf = oc_num_fields(P);
+    double A[OC_MAXF], B[OC_MAXF], C[OC_MAXF], D[OC_MAXF];
+    double F1[OC_MAXF], F2[OC_MAXF], F3[OC_MAXF];
+    for (int f = 0; f < nf; ++f) {
+        A[f] = W[f * PN + cL - stride];
+        B[f] = W[f * PN + cL];
+        C[f] = W[f * PN + cL + stride];
+        D[f] = W[f * PN + cL + 2 * stride];
+    }
+    oc_numerical_flux(P, d, B, C, F1);
+    oc_numerical_flux(P, d, B, D, F2);
+    oc_numerical_flux(P, d, A, C, F3);
+    for (int f = 0; f < nf; ++f)
+        F[f] = ((4.0 / 3.0) * F1[f]) - ((1.0 / 6.0) * (F2[f] + F3[f]));
+}
+
 int oc_rhs(const oc_problem* P, const double* U, double* rhs)
 {
     int st = oc_validate(P);
@@ -694,11 +773,15 @@ int oc_rhs(const oc_problem* P, const double* U, double* rhs)
                     int64_t cR = pidx(&pd, i, j, k);
                     int64_t cL = cR - stride;
                     double UL[OC_MAXF], UR[OC_MAXF], F[OC_MAXF];
-                    for (int f = 0; f < nf; ++f) {
-                        UL[f] = Wp[f * PN + cL];
-                        UR[f] = Wm[f * PN + cR];
+                    if (P->flux == OC_FLUX_EC4) {
+                        ec4_face(P, d, W, PN, cL, stride, F);
+                    } else {
+                        for (int f = 0; f < nf; ++f) {
+                            UL[f] = Wp[f * PN + cL];
+                            UR[f] = Wm[f * PN + cR];
+                        }
+                        oc_numerical_flux(P, d, UL, UR, F);
                     }
-                    oc_numerical_flux(P, d, UL, UR, F);
                     int64_t fi = (k * fy + j) * fx + i;
                     for (int f = 0; f < nf; ++f) Fh[f * NF + fi] = F[f];
                 }
