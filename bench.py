@@ -11,7 +11,7 @@ state already resident in HBM), the roofline of the dominant kernel (the stage k
 timed with HIP events on the library's stream over its own launches) and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh3d|mc|sod|swe2d]
+    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh2d_ec4|kh3d|mc|sod|swe2d]
     python bench.py --copy-calibration     # plain copy of known size, for rocprof counters
 """
 from __future__ import annotations
@@ -80,6 +80,9 @@ WORKLOADS = {
     "kh2d_godunov": dict(name="kh2d_1024x1024_weno3_godunov_ssprk3", dim=2, n=1024,
                          flux="godunov", recon="weno3", integrator="ssprk3", cfl=0.4, batch=1,
                          seed=1912, steps=200, warmup=20, cpu_steps=1),
+    "kh2d_ec4": dict(name="kh2d_1024x1024_fourth_order_entropy_conservative_ssprk3", dim=2,
+                     n=1024, flux="ec4", recon="first_order", integrator="ssprk3", cfl=0.4,
+                     batch=1, seed=1912, steps=400, warmup=20, cpu_steps=2),
     "swe2d": dict(name="swe_circular_dam_break_1024x1024_muscl_hll_ssprk2", eq="swe", dim=2,
                   n=1024, flux="hll", recon="muscl_minmod", integrator="ssprk2", cfl=0.4,
                   batch=1, seed=0, steps=2000, warmup=100, cpu_steps=8),
@@ -101,7 +104,9 @@ WORKLOADS = {
 
 # rocprofv3 summaries of the stage kernel (commands, counters, traffic) per workload
 PROFILE_SUMMARY = {"kh2d": "stage_kernel_kh2d_1024.md", "kh3d": "stage_kernel_kh3d_512.md",
-                   "mc": "stage_kernel_mc_256x1024.md"}
+                   "kh2d_roe": "stage_kernel_kh2d_roe_1024.md", "swe2d": "stage_kernel_swe2d_1024.md",
+                   "kh2d_godunov": "stage_kernel_kh2d_godunov_1024.md",
+                   "kh2d_ec4": "stage_kernel_kh2d_ec4_1024.md"}
 
 
 def initial_state(w):
@@ -122,7 +127,8 @@ def initial_state(w):
 # physics they inline, their tile tables). A change to any of them invalidates the committed
 # traffic counters.
 STAGE_KERNEL_SOURCES = ("fv_common.h", "fv_physics.h", "fv_registry.h", "fv_stage.h",
-                        "fv_stage_z.h", "inst_euler2d_hot.hip", "inst_euler3d_hot.hip")
+                        "fv_stage_z.h", "inst_euler2d_hot.hip", "inst_euler3d_hot.hip",
+                        "inst_more2d.hip", "inst_swe.hip", "inst_godunov.hip", "inst_ec.hip")
 
 
 def kernel_sources_hash() -> str:

@@ -55,14 +55,20 @@ typedef enum { FV_EQ_ADVECTION = 0, FV_EQ_BURGERS = 1, FV_EQ_EULER = 2,
 /* Numerical fluxes (Section 2.1 names HLLC, Godunov, Rusanov, Roe and entropy-conservative
  * fluxes): Rusanov (local Lax--Friedrichs); HLL and HLLC with Davis wave speeds; Roe with
  * Roe's average state and Harten's entropy fix on the acoustic waves (for Burgers the Roe
- * speed (uL + uR)/2 with the fix over a rarefaction fan, for advection upwinding); EC,
- * Tadmor's entropy-conservative flux (uL^2 + uL uR + uR^2)/6, Burgers only; GODUNOV, the
+ * speed (uL + uR)/2 with the fix over a rarefaction fan, for advection upwinding); EC, the
+ * two-point entropy-conservative flux: Tadmor's (uL^2 + uL uR + uR^2)/6 for Burgers,
+ * Chandrashekar's (logarithmic means of rho and rho/(2p)) for Euler; EC4, the fourth-order
+ * entropy-conservative flux of LeFloch, Mercier and Rohde, (4/3) EC(U_i, U_i+1) -
+ * (1/6) (EC(U_i, U_i+2) + EC(U_i-1, U_i+1)) on the cell values, which requires
+ * FV_RECON_FIRST_ORDER (no reconstruction; FV_ENOTSUP otherwise); both EC fluxes are for
+ * Burgers and Euler only, and the Euler ones call log1p(), so they agree with other
+ * implementations to rounding; GODUNOV, the
  * physical flux of the exact Riemann solution at the face (Euler: Toro's star pressure by
  * Newton's method and wave sampling; Burgers: the entropy solution; advection: upwinding),
  * not for shallow water. The Euler Godunov flux calls pow() and stops Newton's method on a
  * step-size test, so it agrees with other implementations to rounding, not bit for bit. */
 typedef enum { FV_FLUX_RUSANOV = 0, FV_FLUX_HLL = 1, FV_FLUX_HLLC = 2, FV_FLUX_ROE = 3,
-               FV_FLUX_EC = 4, FV_FLUX_GODUNOV = 5 } fv_flux;
+               FV_FLUX_EC = 4, FV_FLUX_GODUNOV = 5, FV_FLUX_EC4 = 6 } fv_flux;
 /* Reconstructions (Section 2.1 names ENO and WENO): piecewise constant; MUSCL with the
  * minmod limiter; third-order WENO; second-order ENO (the one-sided difference of smaller
  * magnitude, the left one on a tie). Component-wise on the conserved variables. */

@@ -46,7 +46,8 @@ static std::vector<RegEntry>& registry()
         const RegEntry* (*units[])(int*) = {unit_euler1d, unit_euler2d, unit_euler2d_hot,
                                             unit_euler3d, unit_euler3d_hot, unit_scalar1d,
                                             unit_scalar2d, unit_scalar3d, unit_more1d,
-                                            unit_more2d, unit_more3d, unit_swe, unit_godunov};
+                                            unit_more2d, unit_more3d, unit_swe, unit_godunov,
+                                            unit_ec};
         for (auto u : units) {
             int n = 0;
             const RegEntry* t = u(&n);
@@ -165,10 +166,12 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
         if (!(eq->gravity > 0.0) || !std::isfinite(eq->gravity)) return fail(FV_EINVAL, "gravity must be positive");
         if (grid->dim > 2) return fail(FV_ENOTSUP, "the shallow-water equations are offered in 1D and 2D");
     }
-    if (flux < 0 || flux > 5) return fail(FV_EINVAL, "unknown flux");
+    if (flux < 0 || flux > 6) return fail(FV_EINVAL, "unknown flux");
     if (recon < 0 || recon > 3) return fail(FV_EINVAL, "unknown reconstruction");
-    if (flux == FV_FLUX_EC && eq->kind != FV_EQ_BURGERS)
-        return fail(FV_ENOTSUP, "the entropy-conservative flux is offered for Burgers only");
+    if ((flux == FV_FLUX_EC || flux == FV_FLUX_EC4) && eq->kind != FV_EQ_BURGERS && eq->kind != FV_EQ_EULER)
+        return fail(FV_ENOTSUP, "the entropy-conservative fluxes are offered for Burgers and Euler");
+    if (flux == FV_FLUX_EC4 && recon != FV_RECON_FIRST_ORDER)
+        return fail(FV_ENOTSUP, "the fourth-order entropy-conservative flux takes the cell values (first order)");
     if (flux == FV_FLUX_GODUNOV && eq->kind == FV_EQ_SHALLOW_WATER)
         return fail(FV_ENOTSUP, "Godunov's flux is not offered for the shallow-water equations");
     if (integrator < 0 || integrator > 2) return fail(FV_EINVAL, "unknown integrator");

@@ -8,8 +8,11 @@
 namespace fvk {
 
 enum { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2, EQ_SWE = 3 };
-enum { FLUX_RUSANOV = 0, FLUX_HLL = 1, FLUX_HLLC = 2, FLUX_ROE = 3, FLUX_EC = 4, FLUX_GODUNOV = 5 };
-enum { REC_FIRST = 0, REC_MUSCL = 1, REC_WENO3 = 2, REC_ENO2 = 3 };
+enum { FLUX_RUSANOV = 0, FLUX_HLL = 1, FLUX_HLLC = 2, FLUX_ROE = 3, FLUX_EC = 4, FLUX_GODUNOV = 5,
+       FLUX_EC4 = 6 };
+// REC_CELLS4 is internal to the kernels: a face reads the four cell values i-1..i+2 with no
+// reconstruction (the fourth-order entropy-conservative flux); callers select it as REC_FIRST.
+enum { REC_FIRST = 0, REC_MUSCL = 1, REC_WENO3 = 2, REC_ENO2 = 3, REC_CELLS4 = 4 };
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
 
 // Status codes written into the per-sample error words (same values as fv_status).

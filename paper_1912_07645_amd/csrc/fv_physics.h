@@ -266,6 +266,53 @@ __device__ __forceinline__ void godunov_flux(const double* UL, const double* UR,
     Fh[DIM + 1] = (E + pres) * un;
 }
 
+// Logarithmic mean (a - b) / (ln a - ln b) of a, b > 0 (= a when a = b). With
+// f = (a - b) / (a + b) it is ((a + b) / 2) f / atanh(f); for f^2 < 1e-4 the series
+// f / atanh(f) = 1 / (1 + f^2/3 + f^4/5 + f^6/7 + ...) to the f^6 term (the rest is below
+// 1.2e-17 relative), otherwise ln a - ln b = log1p((a - b) / b), free of cancellation.
+__device__ __forceinline__ double logmean(double a, double b)
+{
+    const double f = (a - b) / (a + b);
+    const double u = f * f;
+    if (u < 1e-4) {
+        const double s = 1.0 + (u * ((1.0 / 3.0) + (u * ((1.0 / 5.0) + (u * (1.0 / 7.0))))));
+        return (0.5 * (a + b)) / s;
+    }
+    return (a - b) / log1p((a - b) / b);
+}
+
+// Chandrashekar's entropy-conservative two-point flux (entropy -rho s / (gamma - 1)): with
+// beta = rho / (2p), logarithmic means of rho and beta, arithmetic means of u_k, rho, beta
+// and |u|^2: F_rho = rho^ u_n, F_m_k = u_k F_rho + p~ delta_kn, p~ = mean rho / (2 mean beta),
+// F_E = (1 / (2 (gamma - 1) beta^) - mean |u|^2 / 2) F_rho + sum_k u_k F_m_k.
+template <int DIM>
+__device__ __forceinline__ void ec_euler_flux(const double* UL, const double* UR, const EulerPrim<DIM>& wl,
+                                              const EulerPrim<DIM>& wr, int nd, double* Fh, const Phys& ph)
+{
+    const double bL = UL[0] / (2.0 * wl.p), bR = UR[0] / (2.0 * wr.p);
+    const double rho_ln = logmean(UL[0], UR[0]);
+    const double beta_ln = logmean(bL, bR);
+    double um[DIM];
+    double qL = wl.u[0] * wl.u[0], qR = wr.u[0] * wr.u[0];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) um[k] = 0.5 * (wl.u[k] + wr.u[k]);
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) {
+        qL = qL + (wl.u[k] * wl.u[k]);
+        qR = qR + (wr.u[k] * wr.u[k]);
+    }
+    const double pt = (0.5 * (UL[0] + UR[0])) / (bL + bR);
+    const double Fr = rho_ln * pick<DIM>(um, nd);
+    Fh[0] = Fr;
+    double Fe = ((1.0 / ((2.0 * ph.gm1) * beta_ln)) - (0.25 * (qL + qR))) * Fr;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        Fh[1 + k] = (um[k] * Fr) + ((k == nd) ? pt : 0.0);
+        Fe = Fe + (um[k] * Fh[1 + k]);
+    }
+    Fh[DIM + 1] = Fe;
+}
+
 // Numerical flux of the Euler equations across a face with normal axis nd.
 template <int DIM, int FLUX>
 __device__ __forceinline__ void euler_numflux(const double* UL, const double* UR, int nd, double* Fh,
@@ -291,6 +338,10 @@ __device__ __forceinline__ void euler_numflux(const double* UL, const double* UR
     }
     if (FLUX == FLUX_GODUNOV) {
         godunov_flux<DIM>(UL, UR, wl, wr, nd, Fh, ph);
+        return;
+    }
+    if (FLUX == FLUX_EC || FLUX == FLUX_EC4) {
+        ec_euler_flux<DIM>(UL, UR, wl, wr, nd, Fh, ph);
         return;
     }
     // Davis wave-speed estimates
@@ -470,7 +521,8 @@ __device__ __forceinline__ double scalar_numflux(double uL, double uR, int nd, c
         const double fan = (EQ == EQ_BURGERS) ? (0.5 * vmax(0.0, uR - uL)) : 0.0;
         return 0.5 * ((FL + FR) - (harten_fix(a, fan) * (uR - uL)));
     }
-    if (FLUX == FLUX_EC) return (((uL * uL) + (uL * uR)) + (uR * uR)) / 6.0;   // Burgers
+    if (FLUX == FLUX_EC || FLUX == FLUX_EC4)                                   // Burgers
+        return (((uL * uL) + (uL * uR)) + (uR * uR)) / 6.0;
     if (FLUX == FLUX_GODUNOV) {
         // exact Riemann solution at x/t = 0: for Burgers a shock (uL > uR) goes the way of its
         // speed (uL + uR)/2, a fan containing 0 gives f(0) = 0; advection upwinds
@@ -495,6 +547,22 @@ __device__ __forceinline__ void numflux(const double* UL, const double* UR, int 
     } else {
         Fh[0] = scalar_numflux<DIM, EQ, FLUX>(UL[0], UR[0], nd, ph);
     }
+}
+
+// Fourth-order entropy-conservative flux (LeFloch, Mercier and Rohde) at the face between
+// cells B and C of the cell values A, B, C, D (i-1..i+2): the combination
+// (4/3) F~(B, C) - (1/6) (F~(B, D) + F~(A, C)) of the two-point entropy-conservative flux F~.
+template <int DIM, int EQ>
+__device__ __forceinline__ void ec4_face(const double* A, const double* B, const double* C,
+                                         const double* D, int nd, double* F, const Phys& ph)
+{
+    constexpr int NF = NumFields<DIM, EQ>::value;
+    double F1[NF], F2[NF], F3[NF];
+    numflux<DIM, EQ, FLUX_EC>(B, C, nd, F1, ph);
+    numflux<DIM, EQ, FLUX_EC>(B, D, nd, F2, ph);
+    numflux<DIM, EQ, FLUX_EC>(A, C, nd, F3, ph);
+#pragma unroll
+    for (int q = 0; q < NF; ++q) F[q] = ((4.0 / 3.0) * F1[q]) - ((1.0 / 6.0) * (F2[q] + F3[q]));
 }
 
 // ---------------------------------------------------------------- reconstruction

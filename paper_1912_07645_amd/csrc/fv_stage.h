@@ -102,17 +102,31 @@ __device__ __forceinline__ void one_face(const double* su, const Phys& ph, int l
     const int fz = l / (EX * EY);
     // LDS index of the cell on the right of the face (the face is its "minus" side)
     const int c = (fz + GZ) * TL::PS + (fy + GY) * TL::RS + (fx + G);
-    double UL[NF], UR[NF];
+    if constexpr (FLUX == FLUX_EC4) {
+        static_assert(RECON == REC_CELLS4, "the fourth-order EC flux reads cell values");
+        double A[NF], B[NF], C[NF], D[NF];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) {
-        const double* s = su + q * TL::QS + c;
-        if (RECON == REC_FIRST) {
-            reconstruct<RECON>(0.0, s[-STRIDE], s[0], 0.0, UL[q], UR[q]);
-        } else {
-            reconstruct<RECON>(s[-2 * STRIDE], s[-STRIDE], s[0], s[STRIDE], UL[q], UR[q]);
+        for (int q = 0; q < NF; ++q) {
+            const double* s = su + q * TL::QS + c;
+            A[q] = s[-2 * STRIDE];
+            B[q] = s[-STRIDE];
+            C[q] = s[0];
+            D[q] = s[STRIDE];
         }
+        ec4_face<DIM, EQ>(A, B, C, D, ND, F, ph);
+    } else {
+        double UL[NF], UR[NF];
+#pragma unroll
+        for (int q = 0; q < NF; ++q) {
+            const double* s = su + q * TL::QS + c;
+            if (RECON == REC_FIRST) {
+                reconstruct<RECON>(0.0, s[-STRIDE], s[0], 0.0, UL[q], UR[q]);
+            } else {
+                reconstruct<RECON>(s[-2 * STRIDE], s[-STRIDE], s[0], s[STRIDE], UL[q], UR[q]);
+            }
+        }
+        numflux<DIM, EQ, FLUX>(UL, UR, ND, F, ph);
     }
-    numflux<DIM, EQ, FLUX>(UL, UR, ND, F, ph);
 }
 
 // Padded face list: each axis's faces rounded up to whole wavefronts, so the faces a

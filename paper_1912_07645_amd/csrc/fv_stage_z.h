@@ -65,6 +65,7 @@ __device__ __forceinline__ void z_halo_pos(int h, int& px, int& py)
 template <int EQ, int RECON, int FLUX, int BX, int BY, int NT, int ND>
 __device__ __forceinline__ void z_plane_face(const double* sp, const Phys& ph, int l, double* F)
 {
+    static_assert(FLUX != FLUX_EC4, "the z-marching kernel has no fourth-order EC path");
     using T = ZTile<EQ, RECON, BX, BY, NT>;
     constexpr int NF = T::NF, G = T::G, PX = T::PX, PP = T::PP;
     constexpr int EX = BX + (ND == 0);

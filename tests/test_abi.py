@@ -61,12 +61,15 @@ def test_argument_validation_without_device():
     with pytest.raises(fv.FVError) as e:
         fv.fv_create(g, fv.make_equation("euler", gamma=1.0), 0, 0, 0)
     assert e.value.status == fv.FV_EINVAL
-    for flux, recon, integ in ((6, 0, 0), (0, 4, 0), (0, 0, 3), (-1, 0, 0)):
+    for flux, recon, integ in ((7, 0, 0), (0, 4, 0), (0, 0, 3), (-1, 0, 0)):
         with pytest.raises(fv.FVError) as e:
             fv.fv_create(g, eq, flux, recon, integ)
         assert e.value.status == fv.FV_EINVAL
-    with pytest.raises(fv.FVError) as e:
-        fv.fv_create(g, eq, fv.FLUX["ec"], 0, 0)        # entropy-conservative: Burgers only
+    with pytest.raises(fv.FVError) as e:                 # entropy-conservative: Burgers, Euler
+        fv.fv_create(g, fv.make_equation("advection"), fv.FLUX["ec"], 0, 0)
+    assert e.value.status == fv.FV_ENOTSUP
+    with pytest.raises(fv.FVError) as e:                 # fourth-order EC: cell values only
+        fv.fv_create(g, eq, fv.FLUX["ec4"], fv.RECON["muscl_minmod"], 0)
     assert e.value.status == fv.FV_ENOTSUP
     with pytest.raises(fv.FVError) as e:
         fv.fv_create(g, fv.make_equation("swe"), fv.FLUX["godunov"], 0, 0)

@@ -72,13 +72,14 @@ def test_kh_weno3_roe_bitwise():
     assert_parity(G, R, what="kh roe")
 
 
-def test_ec_rejected_for_euler_and_advection():
+def test_ec_rejected_for_advection_and_shallow_water():
     import paper_1912_07645_amd.fv as fv
     from paper_1912_07645_amd import Solver
-    for eq in ("euler", "advection"):
-        with pytest.raises(fv.FVError) as e:
-            Solver(dim=1, n=(16,), eq=eq, flux="ec")
-        assert e.value.status == fv.FV_ENOTSUP
+    for eq in ("advection", "swe"):
+        for flux in ("ec", "ec4"):
+            with pytest.raises(fv.FVError) as e:
+                Solver(dim=1, n=(16,), eq=eq, flux=flux)
+            assert e.value.status == fv.FV_ENOTSUP
 
 
 def test_kh_roe_1024_full_size_bitwise():
