@@ -176,8 +176,8 @@ def test_ec_flux_identity_and_entropy_conservation():
     scale = float(np.sum(np.abs(u) * np.abs(O.rhs(pec, u))))
     assert abs(e_ec) <= 1e-13 * scale
     assert e_rs < -1e-3 * scale
-    with pytest.raises(O.OracleError):
-        O.evolve(O.Problem(dim=1, n=(8,), eq="euler", flux="ec"), np.ones((1, 3, 1, 1, 8)), 0.1, 0.4)
+    with pytest.raises(O.OracleError):                   # EC fluxes: Burgers and Euler only
+        O.evolve(O.Problem(dim=1, n=(8,), eq="advection", flux="ec"), np.ones((1, 1, 1, 1, 8)), 0.1, 0.4)
 
 
 def test_eno2_hand_values():
