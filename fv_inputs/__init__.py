@@ -317,6 +317,75 @@ def random_smooth_swe(seed: int, shape_cells, dim: int, batch: int = 1) -> np.nd
     return U
 
 
+def mhd_conserved(rho, u, p, B, gamma: float) -> np.ndarray:
+    """Ideal-MHD conserved fields (rho, m_x, m_y, m_z, E, B_x, B_y, B_z) from density, three
+    velocity components, pressure and three field components (arrays of one shape), with
+    E = p/(gamma - 1) + rho |u|^2 / 2 + |B|^2 / 2."""
+    u = [np.asarray(c, dtype=np.float64) for c in u]
+    B = [np.asarray(c, dtype=np.float64) for c in B]
+    rho = np.asarray(rho, dtype=np.float64)
+    E = p / (gamma - 1.0) + 0.5 * rho * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2) \
+        + 0.5 * (B[0] ** 2 + B[1] ** 2 + B[2] ** 2)
+    return np.stack([rho, rho * u[0], rho * u[1], rho * u[2], E, B[0], B[1], B[2]])
+
+
+def orszag_tang_state(n: int, gamma: float = 5.0 / 3.0) -> np.ndarray:
+    """The Orszag--Tang vortex on the periodic unit square, n x n cells, sampled at cell
+    centres: rho = gamma^2, p = gamma, u = (-sin 2 pi y, sin 2 pi x, 0),
+    B = (-sin 2 pi y, sin 4 pi x, 0). Returns [1][8][1][n][n]."""
+    x = cell_centres(n)[None, :]
+    y = cell_centres(n)[:, None]
+    one = np.ones((n, n))
+    U = mhd_conserved(gamma * gamma * one, [-np.sin(2 * np.pi * y) * one, np.sin(2 * np.pi * x) * one, 0 * one],
+                      gamma * one, [-np.sin(2 * np.pi * y) * one, np.sin(4 * np.pi * x) * one, 0 * one], gamma)
+    return U[None, :, None]
+
+
+def brio_wu_state(n: int, gamma: float = 2.0) -> np.ndarray:
+    """The Brio--Wu shock tube: rho, p, B_y = (1, 1, 1) left of x = 1/2 and (0.125, 0.1, -1)
+    right, B_x = 0.75, at rest. Returns [1][8][1][1][n]."""
+    x = cell_centres(n)
+    left = x < 0.5
+    rho = np.where(left, 1.0, 0.125)
+    p = np.where(left, 1.0, 0.1)
+    z = np.zeros(n)
+    U = mhd_conserved(rho, [z, z, z], p, [0.75 + z, np.where(left, 1.0, -1.0), z], gamma)
+    return U[None, :, None, None]
+
+
+def alfven_wave_average(n: int, t: float, amp: float = 0.1, p0: float = 0.1,
+                        gamma: float = 5.0 / 3.0) -> np.ndarray:
+    """Cell averages at time t of the circularly polarised Alfven wave along x (rho = 1,
+    B_x = 1, so the Alfven speed is 1): B_y = amp sin 2 pi (x - t), B_z = amp cos 2 pi (x - t),
+    u_y = -B_y, u_z = -B_z, u_x = 0, p = p0. Each sinusoid's cell average is its centre value
+    times sin(pi dx) / (pi dx); the energy is constant. Returns [1][8][1][1][n]."""
+    x = cell_centres(n)
+    k = np.sin(np.pi / n) / (np.pi / n)
+    sy = amp * k * np.sin(2 * np.pi * (x - t))
+    sz = amp * k * np.cos(2 * np.pi * (x - t))
+    one = np.ones(n)
+    E = p0 / (gamma - 1.0) + 0.5 * amp * amp + 0.5 * (1.0 + amp * amp)
+    U = np.stack([one, 0 * one, -sy, -sz, E * one, one, sy, sz])
+    return U[None, :, None, None]
+
+
+def random_smooth_mhd(seed: int, shape_cells, dim: int, batch: int = 1,
+                      gamma: float = 5.0 / 3.0) -> np.ndarray:
+    """Smooth periodic MHD data [batch][8][nz][ny][nx]: density, the velocity components and
+    pressure from random_smooth_state (the components beyond dim from a second draw), and a
+    field B of size about 0.6 from a third draw's velocities."""
+    E1 = random_smooth_state(seed, shape_cells, 3, batch=batch, gamma=gamma)
+    E2 = random_smooth_state(seed + 7919, shape_cells, 3, batch=batch, gamma=gamma)
+    rho = E1[:, 0]
+    u = [E1[:, 1 + k] / rho for k in range(3)]
+    ke = 0.5 * rho * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    p = (gamma - 1.0) * (E1[:, 4] - ke)
+    B = [0.5 * E2[:, 1 + k] / E2[:, 0] + 0.2 * (k + 1) for k in range(3)]
+    out = np.stack([mhd_conserved(rho[b], [c[b] for c in u], p[b], [c[b] for c in B], gamma)
+                    for b in range(batch)])
+    return np.ascontiguousarray(out)
+
+
 def constant_state(shape_cells, values, batch: int = 1) -> np.ndarray:
     """Every cell equal to ``values`` (one per field). shape_cells = (nz, ny, nx)."""
     nz, ny, nx = shape_cells

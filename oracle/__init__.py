@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "fv_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
 _SO = os.path.join(_BUILD, "liboracle.so")
 
-EQ = {"advection": 0, "burgers": 1, "euler": 2, "swe": 3}
+EQ = {"advection": 0, "burgers": 1, "euler": 2, "swe": 3, "mhd": 4}
 FLUX = {"rusanov": 0, "hll": 1, "hllc": 2, "roe": 3, "ec": 4, "godunov": 5, "ec4": 6}
 RECON = {"first_order": 0, "muscl_minmod": 1, "weno3": 2, "eno2": 3}
 INTEGRATOR = {"forward_euler": 0, "ssprk2": 1, "ssprk3": 2}
@@ -147,7 +147,7 @@ class Problem:
 
     @property
     def nfields(self) -> int:
-        return {"euler": self.dim + 2, "swe": self.dim + 1}.get(self.eq, 1)
+        return {"euler": self.dim + 2, "swe": self.dim + 1, "mhd": 8}.get(self.eq, 1)
 
     @property
     def cells(self) -> int:

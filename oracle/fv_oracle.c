@@ -56,7 +56,12 @@
  *     values without reconstruction. The Euler flux calls log1p(), which the device library
  *     need not round like this one;
  *   - ENO (Section 2.1) is the second-order ENO reconstruction: the one-sided difference of
- *     smaller magnitude, the left one on a tie.
+ *     smaller magnitude, the left one on a tie;
+ *   - ideal MHD (the introduction names it beside Euler and shallow water as an instance of
+ *     eq. 1.1; no form is given) carries
+ *     (rho, m_x, m_y, m_z, E, B_x, B_y, B_z) in every dimension, magnetic pressure |B|^2 / 2,
+ *     with the Rusanov and HLL fluxes on the fast magnetosonic speed; no divergence cleaning
+ *     (the paper names none).
  */
 #include <math.h>
 #include <stdint.h>
@@ -69,7 +74,7 @@
 
 /* ---------------------------------------------------------------- problem description */
 
-enum { OC_EQ_ADVECTION = 0, OC_EQ_BURGERS = 1, OC_EQ_EULER = 2, OC_EQ_SWE = 3 };
+enum { OC_EQ_ADVECTION = 0, OC_EQ_BURGERS = 1, OC_EQ_EULER = 2, OC_EQ_SWE = 3, OC_EQ_MHD = 4 };
 enum { OC_FLUX_RUSANOV = 0, OC_FLUX_HLL = 1, OC_FLUX_HLLC = 2, OC_FLUX_ROE = 3, OC_FLUX_EC = 4,
        OC_FLUX_GODUNOV = 5, OC_FLUX_EC4 = 6 };
 enum { OC_REC_FIRST = 0, OC_REC_MUSCL = 1, OC_REC_WENO3 = 2, OC_REC_ENO2 = 3 };
@@ -78,7 +83,7 @@ enum { OC_BC_PERIODIC = 0, OC_BC_TRANSMISSIVE = 1 };
 enum { OC_OK = 0, OC_EINVAL = 1, OC_ENOTSUP = 2, OC_ENOMEM = 3,
        OC_ENONPHYS = 5, OC_EMAXSTEPS = 6, OC_ECFL = 7 };
 
-#define OC_MAXF 5
+#define OC_MAXF 8
 
 typedef struct {
     int32_t dim;
@@ -98,6 +103,7 @@ typedef struct {
 int oc_num_fields(const oc_problem* P)
 {
     if (P->eq == OC_EQ_EULER) return P->dim + 2;
+    if (P->eq == OC_EQ_MHD) return 8;
     if (P->eq == OC_EQ_SWE) return P->dim + 1;
     return 1;
 }
@@ -124,7 +130,7 @@ int oc_validate(const oc_problem* P)
         if (k < P->dim && !(P->hi[k] > P->lo[k])) return OC_EINVAL;
         if (P->bc[k] != OC_BC_PERIODIC && P->bc[k] != OC_BC_TRANSMISSIVE) return OC_EINVAL;
     }
-    if (P->eq < 0 || P->eq > 3) return OC_EINVAL;
+    if (P->eq < 0 || P->eq > 4) return OC_EINVAL;
     if (P->flux < 0 || P->flux > 6) return OC_EINVAL;
     if (P->recon < 0 || P->recon > 3) return OC_EINVAL;
     if (P->integrator < 0 || P->integrator > 2) return OC_EINVAL;
@@ -132,7 +138,9 @@ int oc_validate(const oc_problem* P)
     if ((P->flux == OC_FLUX_EC || P->flux == OC_FLUX_EC4) &&
         P->eq != OC_EQ_BURGERS && P->eq != OC_EQ_EULER) return OC_ENOTSUP;
     if (P->flux == OC_FLUX_EC4 && P->recon != OC_REC_FIRST) return OC_ENOTSUP;
-    if (P->eq == OC_EQ_EULER && !(P->gamma > 1.0)) return OC_EINVAL;
+    if ((P->eq == OC_EQ_EULER || P->eq == OC_EQ_MHD) && !(P->gamma > 1.0)) return OC_EINVAL;
+    if (P->eq == OC_EQ_MHD && P->flux != OC_FLUX_RUSANOV && P->flux != OC_FLUX_HLL)
+        return OC_ENOTSUP;
     if (P->eq == OC_EQ_SWE) {
         if (!(P->grav > 0.0)) return OC_EINVAL;
         if (P->dim > 2) return OC_ENOTSUP;
@@ -185,6 +193,54 @@ static void euler_flux(const double* U, const oc_prim* w, int dim, int nd, doubl
         else         F[1 + k] = U[1 + k] * un;
     }
     F[dim + 1] = (U[dim + 1] + w->p) * un;
+}
+
+/* Ideal MHD (rho, m_x, m_y, m_z, E, B_x, B_y, B_z) in units where the magnetic pressure is
+ * |B|^2 / 2; three velocity and field components whatever the dimension. */
+typedef struct {
+    double ir;        /* 1 / rho */
+    double u[3];      /* velocity */
+    double pb;        /* magnetic pressure |B|^2 / 2 */
+    double p;         /* gas pressure (gamma - 1)(E - rho |u|^2 / 2 - |B|^2 / 2) */
+} oc_mhd;
+
+static oc_mhd mhd_prim(const double* U, double gm1)
+{
+    oc_mhd w;
+    w.ir = 1.0 / U[0];
+    for (int k = 0; k < 3; ++k) w.u[k] = U[1 + k] * w.ir;
+    const double ke = 0.5 * (((U[1] * w.u[0]) + (U[2] * w.u[1])) + (U[3] * w.u[2]));
+    w.pb = 0.5 * (((U[5] * U[5]) + (U[6] * U[6])) + (U[7] * U[7]));
+    w.p = gm1 * ((U[4] - ke) - w.pb);
+    return w;
+}
+
+/* Fast magnetosonic speed along axis nd: c_f^2 = (a^2 + b^2 + sqrt((a^2 + b^2)^2 -
+ * 4 a^2 b_n^2)) / 2 with a^2 = gamma p / rho, b^2 = |B|^2 / rho, b_n^2 = B_n^2 / rho. */
+static double mhd_fast(const double* U, const oc_mhd* w, int nd, double gamma)
+{
+    const double a2 = (gamma * w->p) * w->ir;
+    const double b2 = (2.0 * w->pb) * w->ir;
+    const double bn2 = (U[5 + nd] * U[5 + nd]) * w->ir;
+    const double s = a2 + b2;
+    const double disc = dmax(0.0, (s * s) - ((4.0 * a2) * bn2));
+    return sqrt(0.5 * (s + sqrt(disc)));
+}
+
+/* Ideal MHD flux along axis nd: mass m_n; momentum m_k u_n - B_n B_k + (p + |B|^2/2) on k = nd;
+ * energy (E + p + |B|^2/2) u_n - B_n (u . B); induction u_n B_k - B_n u_k (zero for k = nd). */
+static void mhd_flux(const double* U, const oc_mhd* w, int nd, double* F)
+{
+    const double un = w->u[nd], bn = U[5 + nd];
+    const double pt = w->p + w->pb;
+    const double ub = ((w->u[0] * U[5]) + (w->u[1] * U[6])) + (w->u[2] * U[7]);
+    F[0] = U[1 + nd];
+    for (int k = 0; k < 3; ++k) {
+        const double f = (U[1 + k] * un) - (bn * U[5 + k]);
+        F[1 + k] = (k == nd) ? (f + pt) : f;
+        F[5 + k] = (un * U[5 + k]) - (bn * w->u[k]);
+    }
+    F[4] = ((U[4] + pt) * un) - (bn * ub);
 }
 
 /* ---------------------------------------------------------------- numerical fluxes */
@@ -436,6 +492,29 @@ void oc_numerical_flux(const oc_problem* P, int nd, const double* UL, const doub
                        double* Fh)
 {
     const int nf = oc_num_fields(P);
+    if (P->eq == OC_EQ_MHD) {
+        const double gm1 = P->gamma - 1.0;
+        oc_mhd wl = mhd_prim(UL, gm1);
+        oc_mhd wr = mhd_prim(UR, gm1);
+        double FL[OC_MAXF], FR[OC_MAXF];
+        mhd_flux(UL, &wl, nd, FL);
+        mhd_flux(UR, &wr, nd, FR);
+        const double uL = wl.u[nd], uR = wr.u[nd];
+        const double cL = mhd_fast(UL, &wl, nd, P->gamma), cR = mhd_fast(UR, &wr, nd, P->gamma);
+        if (P->flux == OC_FLUX_RUSANOV) {
+            double s = dmax(fabs(uL) + cL, fabs(uR) + cR);
+            for (int q = 0; q < nf; ++q)
+                Fh[q] = 0.5 * ((FL[q] + FR[q]) - (s * (UR[q] - UL[q])));
+            return;
+        }
+        double SL = dmin(uL - cL, uR - cR);
+        double SR = dmax(uL + cL, uR + cR);
+        if (SL >= 0.0) { for (int q = 0; q < nf; ++q) Fh[q] = FL[q]; return; }
+        if (SR <= 0.0) { for (int q = 0; q < nf; ++q) Fh[q] = FR[q]; return; }
+        for (int q = 0; q < nf; ++q)
+            Fh[q] = (((SR * FL[q]) - (SL * FR[q])) + ((SL * SR) * (UR[q] - UL[q]))) / (SR - SL);
+        return;
+    }
     if (P->eq == OC_EQ_SWE) {
         const int dim = P->dim;
         const double g = P->grav;
@@ -833,6 +912,13 @@ void oc_max_speed(const oc_problem* P, const double* U, double* M_out, int* bad_
                 double a = (fabs(w.u[d]) + w.c) * inv_dx(P, d);
                 m = (d == 0) ? a : dmax(m, a);
             }
+        } else if (P->eq == OC_EQ_MHD) {
+            oc_mhd w = mhd_prim(V, gm1);
+            if (!(V[0] > 0.0) || !(w.p > 0.0)) bad = 1;
+            for (int d = 0; d < dim; ++d) {
+                double a = (fabs(w.u[d]) + mhd_fast(V, &w, d, gamma)) * inv_dx(P, d);
+                m = (d == 0) ? a : dmax(m, a);
+            }
         } else if (P->eq == OC_EQ_SWE) {
             oc_swe w = swe_prim(V, dim, P->grav);
             if (!(V[0] > 0.0)) bad = 1;
@@ -971,11 +1057,19 @@ int oc_num_quantities(const oc_problem* P)
 }
 
 /* q[quantity][cells] of one sample: rho, u_k = m_k * (1/rho), E; shallow water h,
- * u_k = hu_k * (1/h); or the scalar itself. */
+ * u_k = hu_k * (1/h); MHD rho, u_x, u_y, u_z, E, B_x, B_y, B_z; or the scalar itself. */
 void oc_quantities(const oc_problem* P, const double* U, double* q)
 {
     const int nf = oc_num_fields(P);
     const int64_t N = cells_of(P);
+    if (P->eq == OC_EQ_MHD) {
+        for (int64_t c = 0; c < N; ++c) {
+            double ir = 1.0 / U[c];
+            for (int f = 0; f < 8; ++f)
+                q[f * N + c] = (f >= 1 && f <= 3) ? (U[f * N + c] * ir) : U[f * N + c];
+        }
+        return;
+    }
     if (P->eq == OC_EQ_SWE) {
         for (int64_t c = 0; c < N; ++c) {
             double ih = 1.0 / U[c];
@@ -1092,6 +1186,11 @@ static double cell_quantity(const oc_problem* P, const double* U, int64_t c, int
     if (P->eq == OC_EQ_SWE && qi > 0) {
         double ih = 1.0 / U[c];
         return U[qi * N + c] * ih;
+    }
+    if (P->eq == OC_EQ_MHD) {
+        if (qi < 1 || qi > 3) return U[qi * N + c];
+        double ir = 1.0 / U[c];
+        return U[qi * N + c] * ir;
     }
     if (P->eq != OC_EQ_EULER || qi == 0 || qi == oc_num_fields(P) - 1) return U[qi * N + c];
     double ir = 1.0 / U[c];
