@@ -11,7 +11,7 @@ state already resident in HBM), the roofline of the dominant kernel (the stage k
 timed with HIP events on the library's stream over its own launches) and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh2d_ec4|kh3d|mc|sod|swe2d]
+    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh2d_ec4|kh3d|mc|sod|swe2d|mhd2d]
     python bench.py --copy-calibration     # plain copy of known size, for rocprof counters
 """
 from __future__ import annotations
@@ -83,6 +83,9 @@ WORKLOADS = {
     "kh2d_ec4": dict(name="kh2d_1024x1024_fourth_order_entropy_conservative_ssprk3", dim=2,
                      n=1024, flux="ec4", recon="first_order", integrator="ssprk3", cfl=0.4,
                      batch=1, seed=1912, steps=400, warmup=20, cpu_steps=2),
+    "mhd2d": dict(name="mhd_orszag_tang_1024x1024_muscl_rusanov_ssprk2", eq="mhd", dim=2, n=1024,
+                  flux="rusanov", recon="muscl_minmod", integrator="ssprk2", cfl=0.4, batch=1,
+                  seed=0, gamma=5.0 / 3.0, steps=1000, warmup=50, cpu_steps=4),
     "swe2d": dict(name="swe_circular_dam_break_1024x1024_muscl_hll_ssprk2", eq="swe", dim=2,
                   n=1024, flux="hll", recon="muscl_minmod", integrator="ssprk2", cfl=0.4,
                   batch=1, seed=0, steps=2000, warmup=100, cpu_steps=8),
@@ -106,7 +109,8 @@ WORKLOADS = {
 PROFILE_SUMMARY = {"kh2d": "stage_kernel_kh2d_1024.md", "kh3d": "stage_kernel_kh3d_512.md",
                    "kh2d_roe": "stage_kernel_kh2d_roe_1024.md", "swe2d": "stage_kernel_swe2d_1024.md",
                    "kh2d_godunov": "stage_kernel_kh2d_godunov_1024.md",
-                   "kh2d_ec4": "stage_kernel_kh2d_ec4_1024.md"}
+                   "kh2d_ec4": "stage_kernel_kh2d_ec4_1024.md",
+                   "mhd2d": "stage_kernel_mhd2d_1024.md"}
 
 
 def initial_state(w):
@@ -114,6 +118,8 @@ def initial_state(w):
     import fv_inputs as fi
     if w.get("eq") == "swe":
         return fi.swe_circular_dam_break(w["n"], batch=w["batch"])
+    if w.get("eq") == "mhd":
+        return fi.orszag_tang_state(w["n"], gamma=w["gamma"])
     if w["dim"] == 1:
         return fi.sod_state(w["n"])
     if w["dim"] == 2:
@@ -128,7 +134,8 @@ def initial_state(w):
 # traffic counters.
 STAGE_KERNEL_SOURCES = ("fv_common.h", "fv_physics.h", "fv_registry.h", "fv_stage.h",
                         "fv_stage_z.h", "inst_euler2d_hot.hip", "inst_euler3d_hot.hip",
-                        "inst_more2d.hip", "inst_swe.hip", "inst_godunov.hip", "inst_ec.hip")
+                        "inst_more2d.hip", "inst_swe.hip", "inst_godunov.hip", "inst_ec.hip",
+                        "inst_mhd.hip")
 
 
 def kernel_sources_hash() -> str:
@@ -160,7 +167,8 @@ def cpu_baseline(w, U0, steps):
     cores = O.set_threads(0)
     p = O.Problem(dim=w["dim"], n=(w["n"],) * w["dim"], eq=w.get("eq", "euler"), flux=w["flux"],
                   recon=w["recon"], integrator=w["integrator"],
-                  bc=("transmissive",) if w["dim"] == 1 else ("periodic",) * 3)
+                  bc=("transmissive",) if w["dim"] == 1 else ("periodic",) * 3,
+                  gamma=w.get("gamma", 1.4))
     samples = min(U0.shape[0], 2)
     U = U0[:samples]
     t0 = time.perf_counter()
@@ -400,7 +408,8 @@ def measure(a, w, steps=None, warmup=None):
     U0 = initial_state(w)
     bc = "transmissive" if w["dim"] == 1 else "periodic"
     s = Solver(dim=w["dim"], n=(w["n"],) * w["dim"], eq=w.get("eq", "euler"), flux=w["flux"],
-               recon=w["recon"], integrator=w["integrator"], bc=bc, device=dev)
+               recon=w["recon"], integrator=w["integrator"], bc=bc, gamma=w.get("gamma", 1.4),
+               device=dev)
     U = torch.from_numpy(U0).to(dev)
     B = U.shape[0]
     t = torch.zeros(B, dtype=torch.float64, device=dev)

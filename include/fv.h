@@ -51,7 +51,7 @@ typedef enum {
 
 typedef enum { FV_BC_PERIODIC = 0, FV_BC_TRANSMISSIVE = 1 } fv_bc;
 typedef enum { FV_EQ_ADVECTION = 0, FV_EQ_BURGERS = 1, FV_EQ_EULER = 2,
-               FV_EQ_SHALLOW_WATER = 3 } fv_eq_kind;
+               FV_EQ_SHALLOW_WATER = 3, FV_EQ_MHD = 4 } fv_eq_kind;
 /* Numerical fluxes (Section 2.1 names HLLC, Godunov, Rusanov, Roe and entropy-conservative
  * fluxes): Rusanov (local Lax--Friedrichs); HLL and HLLC with Davis wave speeds; Roe with
  * Roe's average state and Harten's entropy fix on the acoustic waves (for Burgers the Roe
@@ -93,7 +93,12 @@ typedef struct {
  * p = (gamma - 1)(E - |m|^2 / (2 rho)) (gamma > 1), or the shallow-water equations
  * (h, hu_1..hu_dim) with flux along k (hu_k, hu u_k + g h^2 / 2 e_k), u = hu (1/h),
  * gravity = g > 0, in 1D and 2D (a second workload family; the paper's framework is built
- * for several equations, Section 2.1). */
+ * for several equations, Section 2.1), or ideal MHD (the introduction names it among the
+ * systems of eq. 1.1): eight fields (rho, m_x, m_y, m_z, E, B_x, B_y, B_z) in every dimension,
+ * p = (gamma - 1)(E - |m|^2 / (2 rho) - |B|^2 / 2), flux along k (m_k, m u_k - B_k B +
+ * (p + |B|^2/2) e_k, (E + p + |B|^2/2) u_k - B_k (u . B), u_k B - B_k u), with the Rusanov
+ * and HLL fluxes on the fast magnetosonic speed only (FV_ENOTSUP otherwise) and no
+ * divergence cleaning. Statistics of MHD take (rho, u_x, u_y, u_z, E, B_x, B_y, B_z). */
 typedef struct {
     int32_t kind;          /* fv_eq_kind */
     double gamma;

@@ -47,7 +47,7 @@ static std::vector<RegEntry>& registry()
                                             unit_euler3d, unit_euler3d_hot, unit_scalar1d,
                                             unit_scalar2d, unit_scalar3d, unit_more1d,
                                             unit_more2d, unit_more3d, unit_swe, unit_godunov,
-                                            unit_ec};
+                                            unit_ec, unit_mhd};
         for (auto u : units) {
             int n = 0;
             const RegEntry* t = u(&n);
@@ -161,7 +161,7 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     fv_status st = validate_grid(grid);
     if (st) return st;
     if (!eq) return fail(FV_EINVAL, "equation is NULL");
-    if (eq->kind < 0 || eq->kind > 3) return fail(FV_EINVAL, "unknown equation kind");
+    if (eq->kind < 0 || eq->kind > 4) return fail(FV_EINVAL, "unknown equation kind");
     if (eq->kind == FV_EQ_SHALLOW_WATER) {
         if (!(eq->gravity > 0.0) || !std::isfinite(eq->gravity)) return fail(FV_EINVAL, "gravity must be positive");
         if (grid->dim > 2) return fail(FV_ENOTSUP, "the shallow-water equations are offered in 1D and 2D");
@@ -177,7 +177,10 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     if (integrator < 0 || integrator > 2) return fail(FV_EINVAL, "unknown integrator");
     if (flux == FV_FLUX_HLLC && eq->kind != FV_EQ_EULER)
         return fail(FV_ENOTSUP, "HLLC needs the Euler equations");
-    if (eq->kind == FV_EQ_EULER && !(eq->gamma > 1.0)) return fail(FV_EINVAL, "gamma must exceed 1");
+    if ((eq->kind == FV_EQ_EULER || eq->kind == FV_EQ_MHD) && !(eq->gamma > 1.0))
+        return fail(FV_EINVAL, "gamma must exceed 1");
+    if (eq->kind == FV_EQ_MHD && flux != FV_FLUX_RUSANOV && flux != FV_FLUX_HLL)
+        return fail(FV_ENOTSUP, "ideal MHD is offered with the Rusanov and HLL fluxes");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(eq->velocity[k])) return fail(FV_EINVAL, "velocity must be finite");
     st = check_device();
@@ -192,7 +195,8 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     s->flux = flux;
     s->recon = recon;
     s->integ = integrator;
-    s->nf = eq->kind == FV_EQ_EULER ? grid->dim + 2 : (eq->kind == FV_EQ_SHALLOW_WATER ? grid->dim + 1 : 1);
+    s->nf = eq->kind == FV_EQ_EULER ? grid->dim + 2
+          : (eq->kind == FV_EQ_SHALLOW_WATER ? grid->dim + 1 : (eq->kind == FV_EQ_MHD ? 8 : 1));
     s->cells = grid->n[0] * grid->n[1] * grid->n[2];
     s->variant = 0;
     s->kern = kern;

@@ -7,7 +7,7 @@
 
 namespace fvk {
 
-enum { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2, EQ_SWE = 3 };
+enum { EQ_ADVECTION = 0, EQ_BURGERS = 1, EQ_EULER = 2, EQ_SWE = 3, EQ_MHD = 4 };
 enum { FLUX_RUSANOV = 0, FLUX_HLL = 1, FLUX_HLLC = 2, FLUX_ROE = 3, FLUX_EC = 4, FLUX_GODUNOV = 5,
        FLUX_EC4 = 6 };
 // REC_CELLS4 is internal to the kernels: a face reads the four cell values i-1..i+2 with no

@@ -30,11 +30,13 @@ namespace fvk {
 constexpr int kFnThreads = 256;
 constexpr int kShellMaxH = 64;
 
-// kind: 0 the field itself; 1 Euler (momenta over rho); 2 shallow water (momenta over h).
+// kind: 0 the field itself; 1 Euler (momenta over rho); 2 shallow water (momenta over h);
+// 3 ideal MHD (the three momenta over rho).
 __device__ __forceinline__ double quantity_at(const double* U, int64_t cells, int nf, int kind,
                                               int64_t c, int qi)
 {
-    if (kind == 0 || qi == 0 || (kind == 1 && qi == nf - 1)) return U[(int64_t)qi * cells + c];
+    if (kind == 0 || qi == 0 || (kind == 1 && qi == nf - 1) || (kind == 3 && qi > 3))
+        return U[(int64_t)qi * cells + c];
     const double ir = 1.0 / U[c];
     return U[(int64_t)qi * cells + c] * ir;
 }

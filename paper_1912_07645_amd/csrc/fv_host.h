@@ -72,10 +72,11 @@ inline fv_status ensure_scratch(fv_solver* s, size_t bytes)
 }
 
 // How the statistics turn a state into quantities: 0 the scalar itself; 1 Euler (rho,
-// m_k (1/rho), E); 2 shallow water (h, hu_k (1/h)).
+// m_k (1/rho), E); 2 shallow water (h, hu_k (1/h)); 3 ideal MHD (rho, m_k (1/rho), E, B).
 inline int quantity_kind(const fv_solver* s)
 {
-    return s->eq.kind == FV_EQ_EULER ? 1 : (s->eq.kind == FV_EQ_SHALLOW_WATER ? 2 : 0);
+    return s->eq.kind == FV_EQ_EULER ? 1
+           : (s->eq.kind == FV_EQ_SHALLOW_WATER ? 2 : (s->eq.kind == FV_EQ_MHD ? 3 : 0));
 }
 
 inline int n_stages(int integ) { return integ == FV_INT_FORWARD_EULER ? 1 : (integ == FV_INT_SSPRK2 ? 2 : 3); }

@@ -15,7 +15,8 @@ namespace fvk {
 
 template <int DIM, int EQ>
 struct NumFields {
-    static constexpr int value = (EQ == EQ_EULER) ? DIM + 2 : ((EQ == EQ_SWE) ? DIM + 1 : 1);
+    static constexpr int value =
+        (EQ == EQ_EULER) ? DIM + 2 : ((EQ == EQ_SWE) ? DIM + 1 : ((EQ == EQ_MHD) ? 8 : 1));
 };
 
 __device__ __forceinline__ double vmax(double a, double b) { return (a > b) ? a : b; }
@@ -493,6 +494,94 @@ __device__ __forceinline__ void swe_numflux(const double* UL, const double* UR, 
     }
 }
 
+// ---------------------------------------------------------------- ideal MHD
+
+// Ideal MHD (rho, m_x, m_y, m_z, E, B_x, B_y, B_z) in every dimension, magnetic pressure
+// |B|^2 / 2: velocity m_k (1/rho), magnetic pressure pb, gas pressure
+// (gamma - 1)((E - rho |u|^2 / 2) - pb).
+struct MhdPrim {
+    double ir;
+    double u[3];
+    double pb;
+    double p;
+};
+
+__device__ __forceinline__ MhdPrim mhd_prim(const double* U, const Phys& ph)
+{
+    MhdPrim w;
+    w.ir = 1.0 / U[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w.u[k] = U[1 + k] * w.ir;
+    const double ke = 0.5 * (((U[1] * w.u[0]) + (U[2] * w.u[1])) + (U[3] * w.u[2]));
+    w.pb = 0.5 * (((U[5] * U[5]) + (U[6] * U[6])) + (U[7] * U[7]));
+    w.p = ph.gm1 * ((U[4] - ke) - w.pb);
+    return w;
+}
+
+// Fast magnetosonic speed along axis nd: c_f^2 = (a^2 + b^2 + sqrt((a^2 + b^2)^2 -
+// 4 a^2 b_n^2)) / 2, a^2 = gamma p / rho, b^2 = |B|^2 / rho, b_n^2 = B_n^2 / rho.
+__device__ __forceinline__ double mhd_fast(const double* U, const MhdPrim& w, int nd, const Phys& ph)
+{
+    const double a2 = (ph.gamma * w.p) * w.ir;
+    const double b2 = (2.0 * w.pb) * w.ir;
+    const double bn = (nd == 0) ? U[5] : ((nd == 1) ? U[6] : U[7]);
+    const double bn2 = (bn * bn) * w.ir;
+    const double s = a2 + b2;
+    const double disc = vmax(0.0, (s * s) - ((4.0 * a2) * bn2));
+    return sqrt(0.5 * (s + sqrt(disc)));
+}
+
+// Ideal MHD flux along nd: m_n; m_k u_n - B_n B_k (+ p + pb on k = nd);
+// (E + p + pb) u_n - B_n (u . B); u_n B_k - B_n u_k.
+__device__ __forceinline__ void mhd_flux(const double* U, const MhdPrim& w, int nd, double* F)
+{
+    const double un = (nd == 0) ? w.u[0] : ((nd == 1) ? w.u[1] : w.u[2]);
+    const double bn = (nd == 0) ? U[5] : ((nd == 1) ? U[6] : U[7]);
+    const double pt = w.p + w.pb;
+    const double ub = ((w.u[0] * U[5]) + (w.u[1] * U[6])) + (w.u[2] * U[7]);
+    F[0] = (nd == 0) ? U[1] : ((nd == 1) ? U[2] : U[3]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double f = (U[1 + k] * un) - (bn * U[5 + k]);
+        F[1 + k] = (k == nd) ? (f + pt) : f;
+        F[5 + k] = (un * U[5 + k]) - (bn * w.u[k]);
+    }
+    F[4] = ((U[4] + pt) * un) - (bn * ub);
+}
+
+// Numerical flux of ideal MHD: Rusanov or HLL on the fast magnetosonic speeds (Davis).
+template <int FLUX>
+__device__ __forceinline__ void mhd_numflux(const double* UL, const double* UR, int nd, double* Fh,
+                                            const Phys& ph)
+{
+    static_assert(FLUX == FLUX_RUSANOV || FLUX == FLUX_HLL, "ideal MHD: Rusanov or HLL");
+    const MhdPrim wl = mhd_prim(UL, ph);
+    const MhdPrim wr = mhd_prim(UR, ph);
+    double FL[8], FR[8];
+    mhd_flux(UL, wl, nd, FL);
+    mhd_flux(UR, wr, nd, FR);
+    const double uL = (nd == 0) ? wl.u[0] : ((nd == 1) ? wl.u[1] : wl.u[2]);
+    const double uR = (nd == 0) ? wr.u[0] : ((nd == 1) ? wr.u[1] : wr.u[2]);
+    const double cL = mhd_fast(UL, wl, nd, ph), cR = mhd_fast(UR, wr, nd, ph);
+    if (FLUX == FLUX_RUSANOV) {
+        const double s = vmax(fabs(uL) + cL, fabs(uR) + cR);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Fh[q] = 0.5 * ((FL[q] + FR[q]) - (s * (UR[q] - UL[q])));
+        return;
+    }
+    const double SL = vmin(uL - cL, uR - cR);
+    const double SR = vmax(uL + cL, uR + cR);
+    const bool takeL = (SL >= 0.0);
+    const bool takeR = (SR <= 0.0);
+    const double den = SR - SL;
+    const double slsr = SL * SR;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double mid = (((SR * FL[q]) - (SL * FR[q])) + (slsr * (UR[q] - UL[q]))) / den;
+        Fh[q] = takeL ? FL[q] : (takeR ? FR[q] : mid);
+    }
+}
+
 // ---------------------------------------------------------------- scalar equations
 
 template <int DIM, int EQ, int FLUX>
@@ -544,6 +633,8 @@ __device__ __forceinline__ void numflux(const double* UL, const double* UR, int 
         euler_numflux<DIM, FLUX>(UL, UR, nd, Fh, ph);
     } else if constexpr (EQ == EQ_SWE) {
         swe_numflux<DIM, FLUX>(UL, UR, nd, Fh, ph);
+    } else if constexpr (EQ == EQ_MHD) {
+        mhd_numflux<FLUX>(UL, UR, nd, Fh, ph);
     } else {
         Fh[0] = scalar_numflux<DIM, EQ, FLUX>(UL[0], UR[0], nd, ph);
     }
@@ -645,6 +736,14 @@ __device__ __forceinline__ double cell_speed(const double* U, const Phys& ph, bo
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const double a = (fabs(w.u[k]) + w.c) * ph.inv_dx[k];
+            m = (k == 0) ? a : vmax(m, a);
+        }
+    } else if constexpr (EQ == EQ_MHD) {
+        const MhdPrim w = mhd_prim(U, ph);
+        b = b || !(U[0] > 0.0) || !(w.p > 0.0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const double a = (fabs(w.u[k]) + mhd_fast(U, w, k, ph)) * ph.inv_dx[k];
             m = (k == 0) ? a : vmax(m, a);
         }
     } else if constexpr (EQ == EQ_SWE) {

@@ -27,6 +27,7 @@ FV_DECLARE_UNIT(unit_more2d)
 FV_DECLARE_UNIT(unit_more3d)
 FV_DECLARE_UNIT(unit_godunov)
 FV_DECLARE_UNIT(unit_ec)
+FV_DECLARE_UNIT(unit_mhd)
 FV_DECLARE_UNIT(unit_swe)
 
 }  // namespace fvk

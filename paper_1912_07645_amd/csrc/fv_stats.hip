@@ -12,7 +12,7 @@ namespace fvk {
 // fields of the samples are also written there ([sample][quantity][cells]) for the
 // structure functions, so the state is read once.
 // KIND: 0 the field itself; 1 Euler (the momenta divided by rho); 2 shallow water (the
-// momenta divided by h).
+// momenta divided by h); 3 ideal MHD (the three momenta divided by rho).
 template <int NF, int KIND>
 __global__ void __launch_bounds__(256)
 welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, int64_t count0,
@@ -34,7 +34,7 @@ welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, i
         if (KIND != 0) {
             const double ir = 1.0 / x[0];
 #pragma unroll
-            for (int q = 1; q < ((KIND == 1) ? NF - 1 : NF); ++q) x[q] = x[q] * ir;
+            for (int q = 1; q < ((KIND == 1) ? NF - 1 : ((KIND == 3) ? 4 : NF)); ++q) x[q] = x[q] * ir;
         }
         if (qout) {
             double* Q = qout + (int64_t)b * NF * cells + c;
@@ -277,7 +277,7 @@ welford_diff_kernel(const double* __restrict__ fine, const double* __restrict__ 
             const double irf = 1.0 / xf[0];
             const double irc = 1.0 / xc[0];
 #pragma unroll
-            for (int q = 1; q < ((KIND == 1) ? NF - 1 : NF); ++q) {
+            for (int q = 1; q < ((KIND == 1) ? NF - 1 : ((KIND == 3) ? 4 : NF)); ++q) {
                 xf[q] = xf[q] * irf;
                 xc[q] = xc[q] * irc;
             }
@@ -331,6 +331,7 @@ void launch_welford_diff(int nf, int kind, const double* fine, const double* coa
 #define FV_DIFF(NFV, K) hipLaunchKernelGGL((welford_diff_kernel<NFV, K>), dim3(nb), dim3(256), 0, s, \
                                            fine, coarse, geo, batch, count0, mean, m2)
     if (kind == 0) FV_DIFF(1, 0);
+    else if (kind == 3) FV_DIFF(8, 3);
     else if (kind == 2 && nf == 2) FV_DIFF(2, 2);
     else if (kind == 2) FV_DIFF(3, 2);
     else if (nf == 3) FV_DIFF(3, 1);
@@ -379,6 +380,7 @@ void launch_welford(int nf, int kind, const double* state, int64_t cells, int32_
                     int64_t count0, double* mean, double* m2, double* qout, hipStream_t s)
 {
     if (kind == 0) welford_launch<1, 0>(state, cells, batch, count0, mean, m2, qout, s);
+    else if (kind == 3) welford_launch<8, 3>(state, cells, batch, count0, mean, m2, qout, s);
     else if (kind == 2 && nf == 2) welford_launch<2, 2>(state, cells, batch, count0, mean, m2, qout, s);
     else if (kind == 2) welford_launch<3, 2>(state, cells, batch, count0, mean, m2, qout, s);
     else if (nf == 3) welford_launch<3, 1>(state, cells, batch, count0, mean, m2, qout, s);

@@ -17,7 +17,7 @@ FV_OK, FV_EINVAL, FV_ENOTSUP, FV_ENOMEM, FV_EDEVICE, FV_ENONPHYS, FV_EMAXSTEPS, 
 STATUS_NAMES = {0: "FV_OK", 1: "FV_EINVAL", 2: "FV_ENOTSUP", 3: "FV_ENOMEM", 4: "FV_EDEVICE",
                 5: "FV_ENONPHYS", 6: "FV_EMAXSTEPS", 7: "FV_ECFL"}
 BC = {"periodic": 0, "transmissive": 1}
-EQ = {"advection": 0, "burgers": 1, "euler": 2, "swe": 3}
+EQ = {"advection": 0, "burgers": 1, "euler": 2, "swe": 3, "mhd": 4}
 FLUX = {"rusanov": 0, "hll": 1, "hllc": 2, "roe": 3, "ec": 4, "godunov": 5, "ec4": 6}
 RECON = {"first_order": 0, "muscl_minmod": 1, "weno3": 2, "eno2": 3}
 INTEGRATOR = {"forward_euler": 0, "ssprk2": 1, "ssprk3": 2}

@@ -88,7 +88,7 @@ class Solver:
 
     @property
     def num_quantities(self) -> int:
-        return self.nf if self.names["eq"] in ("euler", "swe") else 1
+        return self.nf if self.names["eq"] in ("euler", "swe", "mhd") else 1
 
     def point_pdf(self, U, quantity, points, lo, hi, nbins, counts=None):
         """Histograms over the samples of U of `quantity` at each cell of `points` (flat cell
