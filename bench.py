@@ -129,18 +129,23 @@ def initial_state(w):
     return fi.kh3d_state(w["n"], cx, px, cz, pz)
 
 
-# The sources that define the stage kernels of the benchmarked workloads (the kernels, the
-# physics they inline, their tile tables). A change to any of them invalidates the committed
-# traffic counters.
-STAGE_KERNEL_SOURCES = ("fv_common.h", "fv_physics.h", "fv_registry.h", "fv_stage.h",
-                        "fv_stage_z.h", "inst_euler2d_hot.hip", "inst_euler3d_hot.hip",
-                        "inst_more2d.hip", "inst_swe.hip", "inst_godunov.hip", "inst_ec.hip",
-                        "inst_mhd.hip")
+# The sources that define the stage kernel of each benchmarked workload: the headers every
+# stage kernel compiles from, plus the instantiation unit that builds the workload's kernel. A
+# change to any of them invalidates that workload's committed traffic counters.
+STAGE_KERNEL_COMMON = ("fv_common.h", "fv_physics.h", "fv_registry.h", "fv_stage.h", "fv_stage_z.h")
+STAGE_KERNEL_UNIT = {"kh2d": "inst_euler2d_hot.hip", "kh3d": "inst_euler3d_hot.hip",
+                     "kh2d_roe": "inst_more2d.hip", "swe2d": "inst_swe.hip",
+                     "kh2d_godunov": "inst_godunov.hip", "kh2d_ec4": "inst_ec.hip",
+                     "mhd2d": "inst_mhd.hip"}
 
 
-def kernel_sources_hash() -> str:
+def stage_kernel_sources(workload: str):
+    return STAGE_KERNEL_COMMON + (STAGE_KERNEL_UNIT[workload],)
+
+
+def kernel_sources_hash(workload: str) -> str:
     h = hashlib.sha256()
-    for name in STAGE_KERNEL_SOURCES:
+    for name in stage_kernel_sources(workload):
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_1912_07645_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
@@ -156,7 +161,8 @@ def measured_traffic(workload: str):
     text = open(path).read()
     m_hash = re.search(r"sources_sha256:\s*([0-9a-f]+)", text)
     m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.e+]+)", text)
-    if not m_hash or not m_val or m_hash.group(1) != kernel_sources_hash():
+    if not m_hash or not m_val or workload not in STAGE_KERNEL_UNIT \
+            or m_hash.group(1) != kernel_sources_hash(workload):
         return None
     return float(m_val.group(1))
 
