@@ -183,9 +183,12 @@ __device__ __forceinline__ void toro_f(const ToroSide& s, double p, double e1, d
 // Godunov's flux: the physical flux of the exact Riemann solution at x/t = 0. The star
 // pressure is the root of f_L(p) + f_R(p) + (u_R - u_L), found by Newton's method from the
 // primitive-variable guess, kept at or above 1e-12 (p_L + p_R) and stopped once a step moves p
-// by at most 1e-14 p, or after 20 steps. At that point the error of p is far below rounding,
-// and f_K(p) and t_K(p) follow from their values at the previous iterate by one linear step
-// (the neglected terms are of order 1e-28). The side of the contact that x/t = 0 lies on
+// by at most 1e-8 p, or after 20 steps. Newton's error after a step of size d is about
+// |f''/(2 f')| d^2, and |f''/f'| p stays below 1 on both branches of f_K (about
+// (1 - (gamma-1)/(2 gamma)) / p on the rarefaction branch), so the new iterate is within
+// 1e-16 p of the root. f_K(p) and t_K(p) then follow from their values at the previous iterate
+// by one linear step, with a neglected term of the same size. The side of the contact that
+// x/t = 0 lies on
 // supplies the tangential velocities; its wave (shock or rarefaction fan) decides between the
 // side's own state, the star state and the fan state. The right side is handled as the left
 // side of the mirrored problem (u -> -u).
@@ -208,7 +211,7 @@ __device__ __forceinline__ void godunov_flux(const double* UL, const double* UR,
         toro_f(sR, p, e1, fR, dfR, tR);
         pold = p;
         p = vmax(floor_p, p - (((fL + fR) + du) / (dfL + dfR)));
-        if (fabs(p - pold) <= (1e-14 * pold)) break;
+        if (fabs(p - pold) <= (1e-8 * pold)) break;
     }
     const double dp = p - pold;
     fL = fL + (dfL * dp);
@@ -286,11 +289,18 @@ __device__ __forceinline__ double logmean(double a, double b)
 // beta = rho / (2p), logarithmic means of rho and beta, arithmetic means of u_k, rho, beta
 // and |u|^2: F_rho = rho^ u_n, F_m_k = u_k F_rho + p~ delta_kn, p~ = mean rho / (2 mean beta),
 // F_E = (1 / (2 (gamma - 1) beta^) - mean |u|^2 / 2) F_rho + sum_k u_k F_m_k.
+// beta = rho / (2 p) of a state with primitives w.
+template <int DIM>
+__device__ __forceinline__ double ec_beta(const double* U, const EulerPrim<DIM>& w)
+{
+    return U[0] / (2.0 * w.p);
+}
+
 template <int DIM>
 __device__ __forceinline__ void ec_euler_flux(const double* UL, const double* UR, const EulerPrim<DIM>& wl,
-                                              const EulerPrim<DIM>& wr, int nd, double* Fh, const Phys& ph)
+                                              const EulerPrim<DIM>& wr, double bL, double bR, int nd,
+                                              double* Fh, const Phys& ph)
 {
-    const double bL = UL[0] / (2.0 * wl.p), bR = UR[0] / (2.0 * wr.p);
     const double rho_ln = logmean(UL[0], UR[0]);
     const double beta_ln = logmean(bL, bR);
     double um[DIM];
@@ -342,7 +352,7 @@ __device__ __forceinline__ void euler_numflux(const double* UL, const double* UR
         return;
     }
     if (FLUX == FLUX_EC || FLUX == FLUX_EC4) {
-        ec_euler_flux<DIM>(UL, UR, wl, wr, nd, Fh, ph);
+        ec_euler_flux<DIM>(UL, UR, wl, wr, ec_beta<DIM>(UL, wl), ec_beta<DIM>(UR, wr), nd, Fh, ph);
         return;
     }
     // Davis wave-speed estimates
@@ -649,9 +659,20 @@ __device__ __forceinline__ void ec4_face(const double* A, const double* B, const
 {
     constexpr int NF = NumFields<DIM, EQ>::value;
     double F1[NF], F2[NF], F3[NF];
-    numflux<DIM, EQ, FLUX_EC>(B, C, nd, F1, ph);
-    numflux<DIM, EQ, FLUX_EC>(B, D, nd, F2, ph);
-    numflux<DIM, EQ, FLUX_EC>(A, C, nd, F3, ph);
+    if constexpr (EQ == EQ_EULER) {
+        // the primitives and beta of each of the four cells once, for the three pairs
+        const EulerPrim<DIM> wa = euler_prim<DIM>(A, ph), wb = euler_prim<DIM>(B, ph);
+        const EulerPrim<DIM> wc = euler_prim<DIM>(C, ph), wd = euler_prim<DIM>(D, ph);
+        const double ba = ec_beta<DIM>(A, wa), bb = ec_beta<DIM>(B, wb);
+        const double bc = ec_beta<DIM>(C, wc), bd = ec_beta<DIM>(D, wd);
+        ec_euler_flux<DIM>(B, C, wb, wc, bb, bc, nd, F1, ph);
+        ec_euler_flux<DIM>(B, D, wb, wd, bb, bd, nd, F2, ph);
+        ec_euler_flux<DIM>(A, C, wa, wc, ba, bc, nd, F3, ph);
+    } else {
+        numflux<DIM, EQ, FLUX_EC>(B, C, nd, F1, ph);
+        numflux<DIM, EQ, FLUX_EC>(B, D, nd, F2, ph);
+        numflux<DIM, EQ, FLUX_EC>(A, C, nd, F3, ph);
+    }
 #pragma unroll
     for (int q = 0; q < NF; ++q) F[q] = ((4.0 / 3.0) * F1[q]) - ((1.0 / 6.0) * (F2[q] + F3[q]));
 }

@@ -6,8 +6,9 @@ Kelvin--Helmholtz shear layer with WENO3.
 
 Burgers and advection are bit for bit (no transcendental functions on that path). For the
 Euler equations both sides call pow() -- the device library's and the C library's, each within
-about an ulp but not the same -- and the GPU stops Newton's method once a step is below 1e-14
-of p while the oracle takes 20 steps; both land on the root to rounding, so the bar is the
+about an ulp but not the same -- and the GPU stops Newton's method once a step is below 1e-8
+of p (the next iterate is then within about 1e-16 p of the root) while the oracle takes 20
+steps; both land on the root to rounding, so the bar is the
 relative L1 of 1e-12 the arithmetic allows (each flux differs by a few ulp; over tens of
 steps this grows by well under a factor of 100), plus 1e-11 in the max norm, and equal step
 counts."""
