@@ -71,6 +71,17 @@ def test_argument_validation_without_device():
     with pytest.raises(fv.FVError) as e:                 # fourth-order EC: cell values only
         fv.fv_create(g, eq, fv.FLUX["ec4"], fv.RECON["muscl_minmod"], 0)
     assert e.value.status == fv.FV_ENOTSUP
+    mhd = fv.make_equation("mhd", gamma=5.0 / 3.0)
+    for flux in ("hllc", "roe", "godunov", "ec", "ec4"):  # ideal MHD: Rusanov and HLL only
+        with pytest.raises(fv.FVError) as e:
+            fv.fv_create(g, mhd, fv.FLUX[flux], 0, 0)
+        assert e.value.status == fv.FV_ENOTSUP
+    with pytest.raises(fv.FVError) as e:
+        fv.fv_create(g, fv.make_equation("mhd", gamma=1.0), 0, 0, 0)
+    assert e.value.status == fv.FV_EINVAL
+    with pytest.raises(fv.FVError) as e:
+        fv.fv_create(g, fv.make_equation(5), 0, 0, 0)
+    assert e.value.status == fv.FV_EINVAL
     with pytest.raises(fv.FVError) as e:
         fv.fv_create(g, fv.make_equation("swe"), fv.FLUX["godunov"], 0, 0)
     assert e.value.status == fv.FV_ENOTSUP
