@@ -215,7 +215,8 @@ fv_status fv_profile_read(const fv_solver* solver, double* stage_ms, int64_t* st
 
 /* Running Monte Carlo statistics (Section 2.2) on the solver's grid. Quantities: Euler
  * (rho, u_1..u_dim, E) with u_k = m_k * (1/rho); shallow water (h, u_1..u_dim) with
- * u_k = hu_k * (1/h); scalar equations the field itself.
+ * u_k = hu_k * (1/h); ideal MHD (rho, u_x, u_y, u_z, E, B_x, B_y, B_z) with
+ * u_k = m_k * (1/rho); scalar equations the field itself.
  * max_h >= 0 is the largest lag of the second-order structure function
  * S_q(h) = 1/(dim N) sum_axes sum_x (q(x + h e_axis) - q(x))^2 (periodic grids only,
  * max_h < n[k] on every axis; FV_ENOTSUP otherwise). */
@@ -258,8 +259,8 @@ fv_status fv_stats_destroy(fv_stats* stats);
 /* Point PDFs (Section 2.2 lists them among the statistics, after Fjordholm, Lye and Mishra):
  * for every cell points[i] (host int64 array of npoints cell indices, x fastest), the
  * histogram over the batch's samples of one quantity (as for fv_stats_create: Euler rho,
- * u_1..u_dim, E with u_k = m_k * (1/rho); shallow water h, u_1..u_dim; scalar equations the
- * field, quantity 0) at that
+ * u_1..u_dim, E with u_k = m_k * (1/rho); shallow water h, u_1..u_dim; ideal MHD rho,
+ * u_x, u_y, u_z, E, B_x, B_y, B_z; scalar equations the field, quantity 0) at that
  * cell. nbins equal bins on [lo, hi): a value v in range goes to bin
  * floor(((v - lo) / (hi - lo)) * nbins) computed in FP64 in that order, or to the last bin
  * if that rounds to nbins. counts: device int64 [npoints][nbins + 2], ADDED to (the caller
