@@ -298,6 +298,24 @@ def run_adjoint(a, w):
             fwd.append(t1 - t0)
             grad.append(t2 - t1)
     tf, tg = sum(fwd) / len(fwd), sum(grad) / len(grad)
+    # the same gradient with binomial checkpointing: less memory, more recomputation
+    snaps = w.get("binomial_snapshots", 10)
+    adjb = Adjoint(s, B, N, dt, cfl_bound=0.6, snapshots=snaps)
+    tb = []
+    for r in range(2):
+        theta = torch.tensor(np.concatenate([c, phi], axis=1), device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Q = LineInitialDataQoI.apply(theta, U0d, Dd, Ed, adjb, j0, j1)
+        Q.sum().backward()
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t1)
+    nst = {"forward_euler": 1, "ssprk2": 2, "ssprk3": 3}[w["integrator"]]
+    binomial = {"snapshots": snaps, "gradient_ms": tb[-1] * 1e3,
+                "recomputed_steps": adjb.recomputed_steps(),
+                "state_copies": snaps + nst + 5,
+                "segment_state_copies": -(-N // adj.every) + adj.every * nst + 4}
+    del adjb
     cells = n * n * B * N
     out = {
         "metric": "FP64 cell-updates/s", "value": cells / tg, "unit": "cell-updates/s",
@@ -308,6 +326,7 @@ def run_adjoint(a, w):
                    "step": "one gradient evaluation (forward with checkpoints + reverse sweep)",
                    "forward_tile": list(s.tile()[0]), "tuned_variant": tuned},
         "forward_ms": tf * 1e3, "gradient_ms": tg * 1e3, "adjoint_over_forward_cost": tg / tf,
+        "binomial_checkpointing": binomial,
         "roofline": None,
     }
     return out
@@ -515,7 +534,8 @@ def measure(a, w, steps=None, warmup=None):
         out["batched_mc"]["config"] = mc["config"]["workload"]
         adj = run_adjoint(argparse.Namespace(steps=1, warmup=1, variant=None), WORKLOADS["adjoint"])
         out["adjoint"] = {k: adj[k] for k in ("forward_ms", "gradient_ms",
-                                               "adjoint_over_forward_cost")}
+                                               "adjoint_over_forward_cost",
+                                               "binomial_checkpointing")}
         out["adjoint"]["config"] = adj["config"]["workload"]
     if w["name"].startswith("kh2d_256x256_x1024"):
         from paper_1912_07645_amd import Stats

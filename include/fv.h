@@ -312,6 +312,22 @@ fv_status fv_structure_shell(const fv_solver* solver, const double* state, int64
 fv_status fv_adjoint_create(fv_solver* solver, int64_t batch, int64_t nsteps, double dt,
                             int64_t every, double cfl_bound, fv_adjoint** out);
 
+/* The same adjoint with binomial checkpointing (Griewank's revolve schedule) instead of
+ * segments: the forward run keeps only the initial state, and the reverse sweep places up to
+ * `snapshots` (>= 0) further checkpoints where the binomial schedule puts them. Reversing
+ * nsteps = l steps then runs p + l forward steps (l = one stage recomputation per step when
+ * the stepper has more than one stage, 0 otherwise), p = t l - C(snapshots + 1 + t, t - 1)
+ * with t the smallest integer such that C(snapshots + 1 + t, t) >= l (p = l (l - 1) / 2 for
+ * snapshots = 0): the fewest for that memory. Device memory: snapshots + stages + 5 states
+ * per batch instead of the segments' ceil(nsteps / every) + every * stages + 4. Same
+ * arguments, errors and gradient (bit for bit) as fv_adjoint_create otherwise. */
+fv_status fv_adjoint_create_binomial(fv_solver* solver, int64_t batch, int64_t nsteps, double dt,
+                                     int64_t snapshots, double cfl_bound, fv_adjoint** out);
+
+/* Forward steps the last fv_adjoint_backward of this handle ran to recompute states (host
+ * int64 out). */
+fv_status fv_adjoint_recomputed_steps(const fv_adjoint* adj, int64_t* steps);
+
 /* Forward run from state0 (device, [batch][fields][cells], not modified) to stateT (device,
  * same shape), storing checkpoints. FV_ENONPHYS / FV_ECFL if a sample's trajectory left the
  * physical states or the CFL bound. */

@@ -18,14 +18,28 @@ from .solver import Solver
 
 
 class Adjoint:
-    """Forward run with checkpoints and reverse sweep for a batch on a solver's grid."""
+    """Forward run with checkpoints and reverse sweep for a batch on a solver's grid.
+
+    Checkpoints every `every` steps (default ceil(sqrt(nsteps))), or, with `snapshots` given,
+    the binomial schedule with that many checkpoint slots besides the initial state."""
 
     def __init__(self, solver: Solver, batch: int, nsteps: int, dt: float, every: int = 0,
-                 cfl_bound: float = 1.0):
+                 cfl_bound: float = 1.0, snapshots: int | None = None):
         self.solver = solver
         self.batch, self.nsteps, self.dt = int(batch), int(nsteps), float(dt)
-        self.every = int(every) if every > 0 else int(math.ceil(math.sqrt(nsteps)))
-        self.handle = fv.fv_adjoint_create(solver.handle, batch, nsteps, dt, self.every, cfl_bound)
+        self.snapshots = None if snapshots is None else int(snapshots)
+        if self.snapshots is None:
+            self.every = int(every) if every > 0 else int(math.ceil(math.sqrt(nsteps)))
+            self.handle = fv.fv_adjoint_create(solver.handle, batch, nsteps, dt, self.every,
+                                               cfl_bound)
+        else:
+            self.every = None
+            self.handle = fv.fv_adjoint_create_binomial(solver.handle, batch, nsteps, dt,
+                                                        self.snapshots, cfl_bound)
+
+    def recomputed_steps(self) -> int:
+        """Forward steps the last reverse sweep ran to recompute states."""
+        return fv.fv_adjoint_recomputed_steps(self.handle)
 
     def __del__(self):
         h = getattr(self, "handle", None)

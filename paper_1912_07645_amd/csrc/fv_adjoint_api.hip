@@ -2,10 +2,18 @@
 // checkpoints, reverse sweep with per-segment recomputation, the kinetic-energy quantity of
 // interest and the line-wise contraction with the initial-data derivative.
 //
-// Checkpointing: the state is stored every `every` steps (every = ceil(sqrt(nsteps)) gives
-// the classical sqrt(N) scheme). The reverse sweep takes the segments last to first; each
-// is recomputed forward from its checkpoint with all Runge--Kutta stage states stored, then
-// reversed stage by stage. Memory: ceil(N / every) + every * stages + 4 states per batch.
+// Checkpointing, two policies.
+// - Segments: the state is stored every `every` steps (every = ceil(sqrt(nsteps)) gives the
+//   classical sqrt(N) scheme). The reverse sweep takes the segments last to first; each is
+//   recomputed forward from its checkpoint with all Runge--Kutta stage states stored, then
+//   reversed stage by stage. Memory: ceil(N / every) + every * stages + 4 states per batch.
+// - Binomial (Griewank's revolve schedule): only the initial state is kept from the forward
+//   run, plus `snapshots` free checkpoint slots. Reversing l steps with s free slots from a
+//   stored state at n0 advances to n0 + m, stores that state in a slot, reverses the last
+//   l - m steps with s - 1 slots, then the first m with s. With the split m chosen as below,
+//   the reverse sweep runs p(l, s + 1) + l forward steps, p the binomial minimum
+//   t l - C(s + 1 + t, t - 1) with C(s + t, t - 1) < l <= C(s + 1 + t, t) (Griewank 1992);
+//   memory snapshots + stages + 5 states per batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +32,10 @@ struct fv_adjoint {
     fv_solver* s = nullptr;
     const AdjKernel* ak = nullptr;
     int64_t batch = 0, nsteps = 0, every = 0, nseg = 0;
+    bool binomial = false;
+    int64_t snapshots = 0;         // binomial: free checkpoint slots besides the initial state
+    double* snap = nullptr;        // binomial: snapshots states
+    int64_t recomputed = 0;        // forward steps run by the last reverse sweep
     double dt = 0.0, cfl_bound = 0.0;
     int nst = 0;
     size_t state_doubles = 0;      // doubles per batch state
@@ -94,8 +106,9 @@ static void forward_step(const fv_adjoint* a, const double* un, double* const* d
     }
 }
 
-extern "C" fv_status fv_adjoint_create(fv_solver* s, int64_t batch, int64_t nsteps, double dt,
-                                       int64_t every, double cfl_bound, fv_adjoint** out)
+static fv_status adjoint_create(fv_solver* s, int64_t batch, int64_t nsteps, double dt,
+                                int64_t every, int64_t snapshots, bool binomial, double cfl_bound,
+                                fv_adjoint** out)
 {
     if (!s || !out) return fail(FV_EINVAL, "NULL argument");
     *out = nullptr;
@@ -106,8 +119,14 @@ extern "C" fv_status fv_adjoint_create(fv_solver* s, int64_t batch, int64_t nste
     if (!ak)
         return fail(FV_ENOTSUP, "the adjoint covers the Euler equations in 1D/2D with the Rusanov "
                                 "flux and first-order or MUSCL-minmod reconstruction");
-    if (every <= 0) every = (int64_t)std::ceil(std::sqrt((double)nsteps));
-    every = std::min(every, nsteps);
+    if (binomial) {
+        if (snapshots < 0) return fail(FV_EINVAL, "snapshots must be >= 0");
+        snapshots = std::min(snapshots, nsteps);
+        every = nsteps;   // the forward run keeps the initial state only
+    } else {
+        if (every <= 0) every = (int64_t)std::ceil(std::sqrt((double)nsteps));
+        every = std::min(every, nsteps);
+    }
     const int64_t tiles = [&] {
         int64_t n = 1;
         const int32_t tb[3] = {ak->bx, ak->by, ak->bz};
@@ -123,14 +142,21 @@ extern "C" fv_status fv_adjoint_create(fv_solver* s, int64_t batch, int64_t nste
     a->nsteps = nsteps;
     a->every = every;
     a->nseg = (nsteps + every - 1) / every;
+    a->binomial = binomial;
+    a->snapshots = snapshots;
     a->dt = dt;
     a->cfl_bound = cfl_bound;
     a->nst = n_stages(s->integ);
     a->state_doubles = (size_t)batch * s->nf * s->cells;
     const size_t sb = sizeof(double) * a->state_doubles;
+    // segment states: every step's stages (segments), or one step's stages plus two work
+    // states (binomial)
+    const int64_t nseg_states = binomial ? a->nst + 2 : every * a->nst + 1;
     bool ok = hipSetDevice(s->device) == hipSuccess &&
               hipMalloc((void**)&a->ckpt, sb * a->nseg) == hipSuccess &&
-              hipMalloc((void**)&a->seg, sb * (every * a->nst + 1)) == hipSuccess &&
+              hipMalloc((void**)&a->seg, sb * nseg_states) == hipSuccess &&
+              (!binomial || snapshots == 0 ||
+               hipMalloc((void**)&a->snap, sb * snapshots) == hipSuccess) &&
               hipMalloc((void**)&a->lam[0], sb) == hipSuccess &&
               hipMalloc((void**)&a->lam[1], sb) == hipSuccess &&
               hipMalloc((void**)&a->lam[2], sb) == hipSuccess &&
@@ -146,12 +172,33 @@ extern "C" fv_status fv_adjoint_create(fv_solver* s, int64_t batch, int64_t nste
     return FV_OK;
 }
 
+extern "C" fv_status fv_adjoint_create(fv_solver* s, int64_t batch, int64_t nsteps, double dt,
+                                       int64_t every, double cfl_bound, fv_adjoint** out)
+{
+    return adjoint_create(s, batch, nsteps, dt, every, 0, false, cfl_bound, out);
+}
+
+extern "C" fv_status fv_adjoint_create_binomial(fv_solver* s, int64_t batch, int64_t nsteps,
+                                                double dt, int64_t snapshots, double cfl_bound,
+                                                fv_adjoint** out)
+{
+    return adjoint_create(s, batch, nsteps, dt, 0, snapshots, true, cfl_bound, out);
+}
+
+extern "C" fv_status fv_adjoint_recomputed_steps(const fv_adjoint* a, int64_t* steps)
+{
+    if (!a || !steps) return fail(FV_EINVAL, "NULL argument");
+    *steps = a->recomputed;
+    return FV_OK;
+}
+
 extern "C" fv_status fv_adjoint_destroy(fv_adjoint* a)
 {
     if (!a) return FV_OK;
     if (a->s && a->s->stream) hipStreamSynchronize(a->s->stream);
     hipFree(a->ckpt);
     hipFree(a->seg);
+    hipFree(a->snap);
     for (double* l : a->lam) hipFree(l);
     hipFree(a->dt_arr);
     hipFree(a->active);
@@ -250,6 +297,126 @@ static fv_status reverse_stage(fv_adjoint* a, const double* U, const double* lam
     return FV_OK;
 }
 
+// Reverse one step: stages[k] holds the state stage k of the step starts from (stages[0] =
+// U^n). lam[*cur] holds dQ/dU^{n+1} on entry and dQ/dU^n on return.
+static void reverse_step(fv_adjoint* a, const double* const* stages, int& cur)
+{
+    const fv_solver* s = a->s;
+    const int S = a->nst;
+    int in = cur, p = (cur + 1) % 3, acc = (cur + 2) % 3;
+    if (S == 1) {
+        reverse_stage(a, stages[0], a->lam[in], a->lam[p], a->lam[acc], 0, 1.0);
+        cur = p;
+        return;
+    }
+    for (int stg = S - 1; stg >= 0; --stg) {
+        const double beta = stage_beta(s->integ, stg);
+        const int mode = (stg == S - 1) ? 0 : (stg == 0 ? 2 : 1);
+        reverse_stage(a, stages[stg], a->lam[in], a->lam[p], a->lam[acc], mode, beta);
+        std::swap(in, p);   // this stage's output is the next stage's input
+    }
+    cur = in;
+}
+
+// Binomial coefficient C(s + t, t) for s, t >= 0, saturated at 2^62 (far above any step
+// count); 0 for t < 0.
+static int64_t binom_st(int64_t s, int64_t t)
+{
+    if (t < 0) return 0;
+    const int64_t k = std::min(s, t), n = s + t;
+    const unsigned __int128 cap = (unsigned __int128)1 << 62;
+    unsigned __int128 r = 1;
+    for (int64_t i = 1; i <= k; ++i) {
+        r = (r * (unsigned __int128)(n - k + i)) / (unsigned __int128)i;   // C(n - k + i, i)
+        if (r >= cap) return (int64_t)cap;
+    }
+    return (int64_t)r;
+}
+
+// The split of the binomial schedule: reversing l >= 2 steps with s >= 1 free slots (s + 1
+// states counting the stored one), store the state after m steps, where t is the smallest
+// integer with C(s + 1 + t, t) >= l and m = min(C(s + t, t - 1), l - C(s + t - 1, t - 1)),
+// the largest split that keeps the binomial minimum.
+static int64_t binomial_split(int64_t l, int64_t s)
+{
+    const int64_t snaps = s + 1;
+    int64_t t = 0;
+    while (binom_st(snaps, t) < l) ++t;
+    int64_t m = std::min(binom_st(snaps, t - 1), l - binom_st(snaps - 1, t - 1));
+    return std::max<int64_t>(1, std::min(m, l - 1));
+}
+
+// Advance k steps from the state `from` into a work buffer; returns the buffer holding the
+// result (`from` itself when k = 0).
+static const double* advance(fv_adjoint* a, const double* from, int64_t k)
+{
+    if (k == 0) return from;
+    const size_t sd = a->state_doubles;
+    const size_t sb = sizeof(double) * sd;
+    hipStream_t st = a->s->stream;
+    double* w0 = a->seg + (size_t)(a->nst + 0) * sd;   // two work states after the stage slots
+    double* w1 = a->seg + (size_t)(a->nst + 1) * sd;
+    hipMemcpyAsync(w0, from, sb, hipMemcpyDeviceToDevice, st);
+    std::vector<double*> dst(a->nst);
+    for (int j = 0; j < a->nst - 1; ++j) dst[j] = a->seg + (size_t)(j + 1) * sd;
+    double* cur = w0;
+    double* other = w1;
+    for (int64_t n = 0; n < k; ++n) {
+        if (a->nst == 1) {
+            dst[0] = other;
+            forward_step(a, cur, dst.data());
+            std::swap(cur, other);
+        } else {
+            dst[a->nst - 1] = cur;   // the last stage writes U^{n+1} over U^n
+            forward_step(a, cur, dst.data());
+        }
+        ++a->recomputed;
+    }
+    return cur;
+}
+
+// Recompute the stage states of the step that starts from U (stages[0] = U) and reverse it.
+static void recompute_and_reverse(fv_adjoint* a, const double* U, int& cur)
+{
+    const size_t sd = a->state_doubles;
+    std::vector<const double*> stages(a->nst);
+    stages[0] = U;
+    if (a->nst > 1) {
+        std::vector<double*> dst(a->nst);
+        for (int j = 0; j < a->nst - 1; ++j) dst[j] = a->seg + (size_t)(j + 1) * sd;
+        // U^{n+1} itself is not needed: it goes to the second work state
+        dst[a->nst - 1] = a->seg + (size_t)(a->nst + 1) * sd;
+        forward_step(a, U, dst.data());
+        ++a->recomputed;
+        for (int j = 1; j < a->nst; ++j) stages[j] = dst[j - 1];
+    }
+    reverse_step(a, stages.data(), cur);
+}
+
+// Reverse steps [n0, n1) from the stored state U_{n0} with s free snapshot slots (slots
+// 0..s-1 of a->snap are free).
+static void revolve(fv_adjoint* a, int64_t n0, int64_t n1, int64_t s, const double* base, int& cur)
+{
+    const int64_t l = n1 - n0;
+    const size_t sd = a->state_doubles;
+    if (l == 1) {
+        recompute_and_reverse(a, base, cur);
+        return;
+    }
+    if (s == 0) {
+        // with several stages advance() leaves its result in the first work state, and the
+        // stage recomputation writes only the stage slots and the second
+        for (int64_t k = n1 - 1; k >= n0; --k) recompute_and_reverse(a, advance(a, base, k - n0), cur);
+        return;
+    }
+    const int64_t m = binomial_split(l, s);
+    double* slot = a->snap + (size_t)(s - 1) * sd;
+    const double* U = advance(a, base, m);
+    hipMemcpyAsync(slot, U, sizeof(double) * sd, hipMemcpyDeviceToDevice, a->s->stream);
+    revolve(a, n0 + m, n1, s - 1, slot, cur);
+    revolve(a, n0, n0 + m, s, base, cur);
+}
+
 extern "C" fv_status fv_adjoint_backward(fv_adjoint* a, const double* dQ_dUT, double* dQ_dU0)
 {
     if (!a || !dQ_dUT || !dQ_dU0) return fail(FV_EINVAL, "NULL argument");
@@ -264,6 +431,14 @@ extern "C" fv_status fv_adjoint_backward(fv_adjoint* a, const double* dQ_dUT, do
     const int S = a->nst;
     int cur = 0;   // lam[cur] holds dQ/dU^{n+1}
     HIP_TRY(hipMemcpyAsync(a->lam[cur], dQ_dUT, sb, hipMemcpyDeviceToDevice, st));
+    a->recomputed = 0;
+    if (a->binomial) {
+        revolve(a, 0, a->nsteps, a->snapshots, a->ckpt, cur);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(dQ_dU0, a->lam[cur], sb, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return stream_leave(s);
+    }
     auto slot = [&](int64_t t, int k) { return a->seg + ((size_t)t * S + k) * sd; };
     for (int64_t sg = a->nseg - 1; sg >= 0; --sg) {
         const int64_t k0 = sg * a->every;
@@ -275,22 +450,13 @@ extern "C" fv_status fv_adjoint_backward(fv_adjoint* a, const double* dQ_dUT, do
             for (int k = 0; k < S - 1; ++k) dst[k] = slot(t, k + 1);
             dst[S - 1] = slot(t + 1, 0);
             forward_step(a, slot(t, 0), dst.data());
+            ++a->recomputed;
         }
         // reverse the segment's steps
+        std::vector<const double*> stages(S);
         for (int64_t t = K - 1; t >= 0; --t) {
-            int in = cur, p = (cur + 1) % 3, acc = (cur + 2) % 3;
-            if (S == 1) {
-                reverse_stage(a, slot(t, 0), a->lam[in], a->lam[p], a->lam[acc], 0, 1.0);
-                cur = p;
-                continue;
-            }
-            for (int stg = S - 1; stg >= 0; --stg) {
-                const double beta = stage_beta(s->integ, stg);
-                const int mode = (stg == S - 1) ? 0 : (stg == 0 ? 2 : 1);
-                reverse_stage(a, slot(t, stg), a->lam[in], a->lam[p], a->lam[acc], mode, beta);
-                std::swap(in, p);   // this stage's output is the next stage's input
-            }
-            cur = in;
+            for (int k = 0; k < S; ++k) stages[k] = slot(t, k);
+            reverse_step(a, stages.data(), cur);
         }
         HIP_TRY(hipGetLastError());
     }

@@ -75,6 +75,8 @@ def _load():
                                i32, vp]),
         "fv_structure_shell": (i32, [vp, vp, i64, i32, i32, i32, vp]),
         "fv_adjoint_create": (i32, [vp, i64, i64, dbl, i64, dbl, C.POINTER(vp)]),
+        "fv_adjoint_create_binomial": (i32, [vp, i64, i64, dbl, i64, dbl, C.POINTER(vp)]),
+        "fv_adjoint_recomputed_steps": (i32, [vp, C.POINTER(i64)]),
         "fv_adjoint_forward": (i32, [vp, vp, vp]),
         "fv_adjoint_backward": (i32, [vp, vp, vp]),
         "fv_adjoint_destroy": (i32, [vp]),
@@ -296,6 +298,19 @@ def fv_adjoint_create(solver, batch, nsteps, dt, every=0, cfl_bound=1.0) -> int:
     check(lib.fv_adjoint_create(solver, int(batch), int(nsteps), float(dt), int(every),
                                 float(cfl_bound), C.byref(h)), "fv_adjoint_create")
     return h.value
+
+
+def fv_adjoint_create_binomial(solver, batch, nsteps, dt, snapshots, cfl_bound=1.0) -> int:
+    h = C.c_void_p()
+    check(lib.fv_adjoint_create_binomial(solver, int(batch), int(nsteps), float(dt), int(snapshots),
+                                         float(cfl_bound), C.byref(h)), "fv_adjoint_create_binomial")
+    return h.value
+
+
+def fv_adjoint_recomputed_steps(adj) -> int:
+    n = C.c_int64()
+    check(lib.fv_adjoint_recomputed_steps(adj, C.byref(n)), "fv_adjoint_recomputed_steps")
+    return n.value
 
 
 def fv_adjoint_forward(adj, state0, stateT) -> None:

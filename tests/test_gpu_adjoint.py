@@ -152,3 +152,46 @@ def test_adjoint_full_configuration_against_finite_differences():
              np.median(rel6), np.percentile(rel6, 90), rel6.max()), flush=True)
     assert np.median(rel_dir) <= 1e-6, rel_dir
     assert np.median(rel6) <= 1e-5, rel6
+
+
+def _binomial_forward_steps(l, snaps):
+    """Griewank's minimal number of forward steps to reverse l steps with `snaps` stored
+    states (the initial one included): t l - C(snaps + t, t - 1) with t the smallest integer
+    such that C(snaps + t, t) >= l; l (l - 1) / 2 for a single stored state."""
+    from math import comb
+    if l <= 1:
+        return 0
+    if snaps == 1:
+        return l * (l - 1) // 2
+    t = 0
+    while comb(snaps + t, t) < l:
+        t += 1
+    return t * l - comb(snaps + t, t - 1)
+
+
+@pytest.mark.parametrize("integ", ["forward_euler", "ssprk3"])
+def test_binomial_checkpointing_equals_segments(integ):
+    """The binomial (revolve) schedule gives the segment schedule's gradient bit for bit, with
+    the published minimal number of recomputed forward steps for each number of snapshots."""
+    torch = torch_gpu()
+    from paper_1912_07645_amd.adjoint import Adjoint
+    n, B, steps = 40, 2, 23
+    U0 = fi.random_smooth_state(77, (1, n, n), 2, batch=B)
+    lamT = np.random.default_rng(8).standard_normal(U0.shape)
+    p = _problem(n, "muscl_minmod", integ)
+    M, _ = O.max_speed(p, U0[0])
+    dt = 0.3 / M
+    s = solver_for(p)
+    ref = Adjoint(s, B, steps, dt, every=5)
+    UT = ref.forward(torch.from_numpy(U0).cuda()).cpu().numpy()
+    g = ref.backward(torch.from_numpy(lamT).cuda()).cpu().numpy()
+    assert ref.recomputed_steps() == steps
+    stage_recompute = 0 if integ == "forward_euler" else steps
+    for snaps in (0, 1, 2, 3, 7, 30):
+        note("binomial adjoint", integ, snaps)
+        adj = Adjoint(s, B, steps, dt, snapshots=snaps)
+        assert np.array_equal(adj.forward(torch.from_numpy(U0).cuda()).cpu().numpy(), UT)
+        gb = adj.backward(torch.from_numpy(lamT).cuda()).cpu().numpy()
+        assert np.array_equal(gb, g), snaps
+        want = _binomial_forward_steps(steps, min(snaps, steps) + 1) + stage_recompute
+        assert adj.recomputed_steps() == want, (snaps, adj.recomputed_steps(), want)
