@@ -499,9 +499,13 @@ def measure(a, w, steps=None, warmup=None):
                 "fp64_ops_per_cell_stage": lane_ops_per_cell_stage(w["dim"], w["integrator"], w["flux"]),
                 "hbm": hbm}
     else:
+        # a 1D run on the single-workgroup variant (tile = the whole grid) has no stage
+        # launches: its "launch" figure is then the device time per stage of the one kernel
+        small = w["dim"] == 1 and tile[0] == w["n"]
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": hbm["traffic"],
-                "kernel": "stage_kernel", "avg_launch_us": avg_launch_s * 1e6,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None if small else hbm["traffic"],
+                "kernel": "small1d_kernel" if small else "stage_kernel",
+                "avg_launch_us": avg_launch_s * 1e6,
                 "algorithmic_bytes_per_launch": bytes_per_launch}
 
     out = {
@@ -537,6 +541,27 @@ def measure(a, w, steps=None, warmup=None):
                                                "adjoint_over_forward_cost",
                                                "binomial_checkpointing")}
         out["adjoint"]["config"] = adj["config"]["workload"]
+    if w["name"].startswith("sod"):
+        # the latency-bound configuration: time to solution (T = 0.2) on the tiled path and
+        # on the single-workgroup time loop
+        tts = {}
+        variants = [("tiled", 0)]
+        s.set_variant(s.num_variants() - 1)
+        if s.num_variants() > 1 and s.tile()[0][0] == w["n"]:
+            variants.append(("single_workgroup", s.num_variants() - 1))
+        for name, v in variants:
+            s.set_variant(v)
+            for r in range(2):
+                U2 = torch.from_numpy(U0).to(dev)
+                t2 = torch.zeros(B, dtype=torch.float64, device=dev)
+                k2 = torch.zeros(B, dtype=torch.int64, device=dev)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.evolve(U2, t2, 0.2, w["cfl"], 10**6, k2, err)
+                torch.cuda.synchronize()
+                el2 = time.perf_counter() - t0
+            tts[name] = {"ms": el2 * 1e3, "steps": int(k2[0])}
+        out["time_to_solution_T0.2"] = tts
     if w["name"].startswith("kh2d_256x256_x1024"):
         from paper_1912_07645_amd import Stats
         out["mc_sample_steps_per_s"] = B * K / el

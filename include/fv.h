@@ -182,10 +182,15 @@ fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers, double* c
 /* ------------------------------------------------------------------ tile tuning */
 
 /* Tile shapes: each (dimension, equation, reconstruction, flux) has one or more compiled
- * tile shapes ("variants"), all producing bit-identical results. fv_num_variants returns
- * their number (-1 on NULL); fv_set_variant selects one (FV_EINVAL if out of range);
- * fv_get_tile reports the current tile shape in cells and its variant index (any output
- * may be NULL). */
+ * tile shapes ("variants"), all producing bit-identical results. A 1D grid small enough for
+ * one workgroup's LDS (Euler up to 1277 cells with two ghost layers, scalar equations up to
+ * 3837; Rusanov, HLL, HLLC and Roe) has one more, last variant: the whole time loop of each
+ * sample in one workgroup (state in LDS, the step decision on the chip, one launch per
+ * 65 536 steps), for latency-bound small problems; its tile is the whole grid. Step
+ * profiling (fv_profile_enable) and fv_evolve_multi use the tiled kernels.
+ * fv_num_variants returns their number (-1 on NULL); fv_set_variant selects one (FV_EINVAL
+ * if out of range); fv_get_tile reports the current tile shape in cells and its variant
+ * index (any output may be NULL). */
 int32_t fv_num_variants(const fv_solver* solver);
 fv_status fv_set_variant(fv_solver* solver, int32_t variant);
 fv_status fv_get_tile(const fv_solver* solver, int32_t* bx, int32_t* by, int32_t* bz,

@@ -215,12 +215,20 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
         fv_destroy(s);
         return fail(FV_EDEVICE, std::string("fv_create: ") + hipGetErrorString(e));
     }
+    if (grid->dim == 1) {
+        const SmallKernel* sk = find_small_kernel(eq->kind, recon, flux);
+        if (sk && grid->n[0] <= sk->max_cells) s->small = sk;
+    }
     // The tuner's stored choice for this shape, if any.
     const char* v = std::getenv("FV_VARIANT");
     if (v) {
         int vi = std::atoi(v);
         const StageKernel* k2 = find_stage_kernel(grid->dim, eq->kind, recon, flux, vi);
         if (k2) { s->variant = vi; s->kern = k2; }
+        else if (s->small && vi == num_stage_variants(grid->dim, eq->kind, recon, flux)) {
+            s->variant = vi;
+            s->use_small = true;
+        }
     }
     *out = s;
     return FV_OK;
@@ -593,6 +601,58 @@ static fv_status evolve_common(fv_solver* s, double* state, int64_t batch, doubl
     }();
     if (blocks_per_sample * batch > 0x7fffffffLL) return fail(FV_EINVAL, "launch too large");
     HIP_TRY(hipSetDevice(s->device));
+    if (s->use_small && !s->profile) {
+        // the single-workgroup time loop: each launch runs every sample up to kSmallChunk
+        // steps; launches repeat while samples still run
+        constexpr int64_t kSmallChunk = 1 << 16;
+        const size_t nb = (size_t)batch;
+        // scratch: running flags, the running count, and step counts / status where the
+        // caller passes none
+        const size_t off_count = sizeof(int32_t) * nb;
+        const size_t off_steps = (off_count + sizeof(int32_t) + 7) & ~(size_t)7;
+        const size_t off_err = off_steps + sizeof(int64_t) * nb;
+        fv_status st = ensure_scratch(s, off_err + sizeof(int32_t) * nb);
+        if (st) return st;
+        st = stream_enter(s);
+        if (st) return st;
+        char* sc = (char*)s->scratch;
+        SmallArgs a{};
+        a.state = state;
+        a.batch = batch;
+        a.n = (int32_t)s->grid.n[0];
+        a.bc = s->grid.bc[0];
+        a.ph = s->ph;
+        a.t = fixed ? nullptr : t;
+        a.steps = steps ? steps : (int64_t*)(sc + off_steps);
+        a.err = err ? err : (int32_t*)(sc + off_err);
+        a.running = (int32_t*)sc;
+        a.n_running = (int32_t*)(sc + off_count);
+        a.chunk = kSmallChunk;
+        a.t_end = t_end;
+        a.cfl = cfl;
+        a.max_steps = max_steps;
+        a.limit_is_error = limit_is_error ? 1 : 0;
+        a.fixed = fixed ? 1 : 0;
+        a.fixed_dt = fixed_dt;
+        a.cfl_bound = cfl_bound;
+        a.nst = n_stages(s->integ);
+        for (int k = 0; k < a.nst; ++k) a.beta[k] = stage_beta(s->integ, k);
+        for (a.first = 1;; a.first = 0) {
+            HIP_TRY(hipMemsetAsync(a.n_running, 0, sizeof(int32_t), s->stream));
+            s->small->launch(a, s->stream);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(s->host_count, a.n_running, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   s->stream));
+            HIP_TRY(hipStreamSynchronize(s->stream));
+            if (s->host_count[0] == 0) break;
+        }
+        fv_status result = FV_OK;
+        st = first_error(s, a.err, batch, &result);
+        if (st) return st;
+        st = stream_leave(s);
+        if (st) return st;
+        return result;
+    }
     WsLayout L = ws_layout(s, batch);
     fv_status st = ensure_workspace(s, L.total);
     if (st) return st;
@@ -719,27 +779,31 @@ extern "C" fv_status fv_profile_read(const fv_solver* s, double* stage_ms, int64
 
 extern "C" int32_t fv_num_variants(const fv_solver* s)
 {
-    return s ? num_stage_variants(s->grid.dim, s->eq.kind, s->recon, s->flux) : -1;
+    if (!s) return -1;
+    return num_stage_variants(s->grid.dim, s->eq.kind, s->recon, s->flux) + (s->small ? 1 : 0);
 }
 
 extern "C" fv_status fv_set_variant(fv_solver* s, int32_t variant)
 {
     if (!s) return fail(FV_EINVAL, "solver is NULL");
     const StageKernel* k = find_stage_kernel(s->grid.dim, s->eq.kind, s->recon, s->flux, variant);
-    if (!k) return fail(FV_EINVAL, "no such variant");
+    const bool small = !k && s->small &&
+                       variant == num_stage_variants(s->grid.dim, s->eq.kind, s->recon, s->flux);
+    if (!k && !small) return fail(FV_EINVAL, "no such variant");
     HIP_TRY(hipStreamSynchronize(s->stream));
     drop_graph(s);
     s->variant = variant;
-    s->kern = k;
+    s->use_small = small;
+    if (k) s->kern = k;   // the single-workgroup variant keeps the tiled kernel for other calls
     return FV_OK;
 }
 
 extern "C" fv_status fv_get_tile(const fv_solver* s, int32_t* bx, int32_t* by, int32_t* bz, int32_t* variant)
 {
     if (!s) return fail(FV_EINVAL, "solver is NULL");
-    if (bx) *bx = s->kern->bx;
-    if (by) *by = s->kern->by;
-    if (bz) *bz = s->kern->bz;
+    if (bx) *bx = s->use_small ? (int32_t)s->grid.n[0] : s->kern->bx;   // one workgroup per sample
+    if (by) *by = s->use_small ? 1 : s->kern->by;
+    if (bz) *bz = s->use_small ? 1 : s->kern->bz;
     if (variant) *variant = s->variant;
     return FV_OK;
 }

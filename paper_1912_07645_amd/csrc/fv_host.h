@@ -9,6 +9,7 @@
 
 #include "../../include/fv.h"
 #include "fv_common.h"
+#include "fv_small.h"
 
 extern thread_local std::string g_last_error;
 
@@ -38,6 +39,10 @@ struct fv_solver {
     int64_t cells;
     int32_t variant;
     const fvk::StageKernel* kern;
+    // 1D grids small enough for one workgroup: the single-workgroup time loop, offered as
+    // the variant after the tiled ones (use_small when it is the selected variant)
+    const fvk::SmallKernel* small = nullptr;
+    bool use_small = false;
     fvk::Phys ph;
     int device;
     hipStream_t user_stream = nullptr;
