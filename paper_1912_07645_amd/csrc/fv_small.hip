@@ -164,16 +164,10 @@ __global__ void __launch_bounds__(kSmallThreads) small1d_kernel(const SmallArgs 
                         const double up = su[q * PX + G + c];
                         const double u0 = use_un ? un[k][q] : up;
                         out[k][q] = u0 + (beta * ((up - u0) + (dt * rhs)));
+                        // in this phase a thread reads only its own cells' state, so the new
+                        // value can replace it at once
+                        su[q * PX + G + c] = out[k][q];
                     }
-                }
-            }
-            __syncthreads();   // every face and state value of this stage has been read
-#pragma unroll
-            for (int k = 0; k < kSmallMaxCpt; ++k) {
-                const int c = threadIdx.x + k * NT;
-                if (c < n) {
-#pragma unroll
-                    for (int q = 0; q < NF; ++q) su[q * PX + G + c] = out[k][q];
                 }
             }
             __syncthreads();
