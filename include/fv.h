@@ -183,8 +183,9 @@ fv_status fv_evolve_multi(int32_t n_groups, fv_solver* const* solvers, double* c
 
 /* Tile shapes: each (dimension, equation, reconstruction, flux) has one or more compiled
  * tile shapes ("variants"), all producing bit-identical results. A 1D grid small enough for
- * one workgroup's LDS (Euler up to 1277 cells with two ghost layers, scalar equations up to
- * 3837; Rusanov, HLL, HLLC and Roe) has one more, last variant: the whole time loop of each
+ * one workgroup's LDS (with two ghost layers: Euler up to 1277 cells, shallow water 1917,
+ * ideal MHD 477, scalar equations 3837; every flux but the fourth-order EC one) has one
+ * more, last variant: the whole time loop of each
  * sample in one workgroup (state in LDS, the step decision on the chip, one launch per
  * 65 536 steps), for latency-bound small problems; its tile is the whole grid. Step
  * profiling (fv_profile_enable) and fv_evolve_multi use the tiled kernels.

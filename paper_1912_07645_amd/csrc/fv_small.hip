@@ -2,7 +2,7 @@
 //
 // A 1D grid of up to a few thousand cells is latency-bound on the tiled path: each step is a
 // handful of tiny launches (stages and the step decision) of a few microseconds each. Here one
-// workgroup of 1024 threads keeps its sample's state in LDS (with the ghost layers) and U^n in
+// workgroup of 1024 threads (512 for the heaviest faces) keeps its sample's state in LDS (with the ghost layers) and U^n in
 // registers, and runs every step on the chip: the step decision, the stages (faces into LDS,
 // divergence and Runge--Kutta combination, ghost refresh) and the wave-speed reduction, until
 // the sample stops or has taken `chunk` steps in this launch (the host launches again while
@@ -15,19 +15,27 @@
 
 namespace fvk {
 
-constexpr int kSmallThreads = 1024;
+// Threads per workgroup: 1024, or 512 where a face needs more registers than 1024 threads
+// leave (128 each): ideal MHD's eight fields and the Euler Godunov flux's Newton iteration.
+template <int EQ, int FLUX>
+constexpr int small_threads() { return (EQ == EQ_MHD || (EQ == EQ_EULER && FLUX == FLUX_GODUNOV)) ? 512 : 1024; }
 
-// Cells per thread: 4 for a scalar equation, 2 for systems (whose registers would spill at 4).
-template <int NF>
-constexpr int small_cpt() { return NF >= 3 ? 2 : 4; }
+// Cells per thread: 4 for a scalar equation, 2 for small systems (3 with 512 threads), 1 for
+// MHD (LDS caps its grids below the thread count).
+template <int EQ, int FLUX>
+constexpr int small_cpt()
+{
+    constexpr int NF = NumFields<1, EQ>::value;
+    return NF >= 5 ? 1 : (NF >= 2 ? (small_threads<EQ, FLUX>() == 512 ? 3 : 2) : 4);
+}
 
 template <int EQ, int RECON, int FLUX>
-__global__ void __launch_bounds__(kSmallThreads) small1d_kernel(const SmallArgs a)
+__global__ void __launch_bounds__((small_threads<EQ, FLUX>())) small1d_kernel(const SmallArgs a)
 {
     constexpr int NF = NumFields<1, EQ>::value;
     constexpr int G = Ghost<RECON>::value;
-    constexpr int NT = kSmallThreads;
-    constexpr int kSmallMaxCpt = small_cpt<NF>();
+    constexpr int NT = small_threads<EQ, FLUX>();
+    constexpr int kSmallMaxCpt = small_cpt<EQ, FLUX>();
     extern __shared__ double lds[];
     const int n = a.n;
     const int PX = n + 2 * G;
@@ -205,7 +213,7 @@ static void launch_small(const SmallArgs& a, hipStream_t s)
     constexpr int G = Ghost<RECON>::value;
     const size_t lds = sizeof(double) * (size_t)NF * ((a.n + 2 * G) + (a.n + 1));
     hipLaunchKernelGGL((small1d_kernel<EQ, RECON, FLUX>), dim3((unsigned)a.batch),
-                       dim3(kSmallThreads), lds, s, a);
+                       dim3(small_threads<EQ, FLUX>()), lds, s, a);
 }
 
 template <int EQ, int RECON, int FLUX>
@@ -215,7 +223,7 @@ constexpr SmallKernel make_small()
     constexpr int G = Ghost<RECON>::value;
     // LDS of the state with ghosts and the faces within 60 KiB, and the cells per thread
     constexpr int by_lds = (60 * 1024 / (8 * NF) - 2 * G - 1) / 2;
-    constexpr int cap = kSmallThreads * small_cpt<NF>();
+    constexpr int cap = small_threads<EQ, FLUX>() * small_cpt<EQ, FLUX>();
     return SmallKernel{EQ, RECON, FLUX, &launch_small<EQ, RECON, FLUX>, by_lds < cap ? by_lds : cap};
 }
 
@@ -223,9 +231,13 @@ constexpr SmallKernel make_small()
                      make_small<E, REC_WENO3, F>(), make_small<E, REC_ENO2, F>()
 static const SmallKernel kSmall[] = {
     SMALL4(EQ_EULER, FLUX_RUSANOV), SMALL4(EQ_EULER, FLUX_HLL), SMALL4(EQ_EULER, FLUX_HLLC),
-    SMALL4(EQ_EULER, FLUX_ROE),
+    SMALL4(EQ_EULER, FLUX_ROE), SMALL4(EQ_EULER, FLUX_GODUNOV), SMALL4(EQ_EULER, FLUX_EC),
     SMALL4(EQ_BURGERS, FLUX_RUSANOV), SMALL4(EQ_BURGERS, FLUX_HLL), SMALL4(EQ_BURGERS, FLUX_ROE),
+    SMALL4(EQ_BURGERS, FLUX_GODUNOV), SMALL4(EQ_BURGERS, FLUX_EC),
     SMALL4(EQ_ADVECTION, FLUX_RUSANOV), SMALL4(EQ_ADVECTION, FLUX_HLL), SMALL4(EQ_ADVECTION, FLUX_ROE),
+    SMALL4(EQ_ADVECTION, FLUX_GODUNOV),
+    SMALL4(EQ_SWE, FLUX_RUSANOV), SMALL4(EQ_SWE, FLUX_HLL), SMALL4(EQ_SWE, FLUX_ROE),
+    SMALL4(EQ_MHD, FLUX_RUSANOV), SMALL4(EQ_MHD, FLUX_HLL),
 };
 #undef SMALL4
 

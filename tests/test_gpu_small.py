@@ -1,4 +1,5 @@
-"""The single-workgroup time loop for small 1D grids (offered as the last tile variant):
+"""The single-workgroup time loop for small 1D grids (offered as the last tile variant), for
+every 1D equation and flux except the fourth-order EC flux:
 bit for bit against the oracle and against the tiled path -- states, times, step counts and
 per-sample status -- for every 1D scheme it is built for, every stepper and both boundary
 kinds, on grids from 1 cell to its largest; the Sod configuration; runs longer than one
@@ -14,8 +15,13 @@ from gpu_helpers import assert_parity, gpu_evolve, note, solver_for, torch_gpu
 pytestmark = pytest.mark.gpu
 
 RECONS = ("first_order", "muscl_minmod", "weno3", "eno2")
-PAIRS = ([("euler", f) for f in ("rusanov", "hll", "hllc", "roe")] +
-         [(e, f) for e in ("burgers", "advection") for f in ("rusanov", "hll", "roe")])
+PAIRS = ([("euler", f) for f in ("rusanov", "hll", "hllc", "roe", "godunov", "ec")] +
+         [("burgers", f) for f in ("rusanov", "hll", "roe", "godunov", "ec")] +
+         [("advection", f) for f in ("rusanov", "hll", "roe", "godunov")] +
+         [("swe", f) for f in ("rusanov", "hll", "roe")] + [("mhd", f) for f in ("rusanov", "hll")])
+# the Euler Godunov and entropy-conservative fluxes call pow/exp/log: against the oracle they
+# agree to rounding (as on the tiled path); against the tiled path bit for bit
+ROUNDING = {("euler", "godunov"), ("euler", "ec")}
 COMBOS = [(eq, fl, rc, it) for eq, fl in PAIRS for rc in RECONS
           for it in ("forward_euler", "ssprk2", "ssprk3")]
 
@@ -30,6 +36,10 @@ def _small_variant(s):
 
 def _initial(p, seed, batch=3):
     nx = p.n[0]
+    if p.eq == "swe":
+        return fi.random_smooth_swe(seed, (1, 1, nx), 1, batch=batch)
+    if p.eq == "mhd":
+        return fi.random_smooth_mhd(seed, (1, 1, nx), 1, batch=batch)
     if p.eq == "euler":
         return fi.random_smooth_state(seed, (1, 1, nx), 1, batch=batch)
     rng = np.random.default_rng(seed)
@@ -42,20 +52,34 @@ def test_small_matches_oracle_and_tiled(eq, flux, recon, integ):
     idx = COMBOS.index((eq, flux, recon, integ))
     bc = "transmissive" if idx % 2 == 0 else "periodic"
     n = (600, 37, 1, 1024, 5)[idx % 5]
+    if eq == "mhd":
+        n = min(n, 477)          # the largest MHD grid the single workgroup takes
     p = O.Problem(dim=1, n=(n,), eq=eq, flux=flux, recon=recon, integrator=integ, bc=(bc,),
-                  vel=(0.7, 0.0, 0.0))
+                  vel=(0.7, 0.0, 0.0), gamma=5.0 / 3.0 if eq == "mhd" else 1.4)
     U0 = _initial(p, 11 + idx)
     note("small", eq, flux, recon, integ, bc, n)
     K = 7
-    R, rt, rs, re = O.evolve(p, U0, 1e3, 0.4, max_steps=K)
+    R, rt, rs, rerr = O.evolve(p, U0, 1e3, 0.4, max_steps=K)
     s = solver_for(p)
     G0, t0, s0, e0, st0 = gpu_evolve(p, U0, 1e3, 0.4, max_steps=K, mode="advance", solver=s)
     _small_variant(s)
     G1, t1, s1, e1, st1 = gpu_evolve(p, U0, 1e3, 0.4, max_steps=K, mode="advance", solver=s)
-    assert st1 == st0 == 0 and np.all(s1 == K) and np.all(e1 == 0)
-    assert np.array_equal(t1, t0) and np.array_equal(t1, rt)
-    assert np.array_equal(G1, G0)
-    assert_parity(G1, R, what=f"small {eq} {flux} {recon} {integ} {bc} {n}")
+    # the oracle reports the step limit as status 6; advance takes it as a plain stop. (An
+    # entropy-conservative flux without dissipation can leave the physical states, which both
+    # sides report alike.)
+    want = np.where(rerr == 6, 0, rerr)
+    assert np.array_equal(e0, want) and np.array_equal(e1, want) and st1 == st0
+    assert np.array_equal(s1, s0) and np.all(s1[rerr == 6] == K)
+    # a sample that failed may hold NaN from its last step, alike on both paths
+    assert np.array_equal(t1, t0) and np.array_equal(G1, G0, equal_nan=True)
+    what = f"small {eq} {flux} {recon} {integ} {bc} {n}"
+    ok = rerr == 6
+    if (eq, flux) in ROUNDING:
+        assert np.allclose(t1, rt, rtol=1e-13, atol=0.0)
+        assert_parity(G1[ok], R[ok], tol=1e-12, bitwise=False, what=what)
+    else:
+        assert np.array_equal(t1, rt)
+        assert_parity(G1[ok], R[ok], what=what)
 
 
 def test_small_sod_full_configuration():
