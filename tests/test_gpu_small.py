@@ -164,3 +164,20 @@ def test_small_stop_rules():
     assert list(ad[3]) == [0, fv.FV_ENONPHYS, 0] and list(ad[2]) == [4, 0, 4]
     assert list(fx[3]) == [0, fv.FV_ENONPHYS, 0]
     assert list(fb[3]) == [fv.FV_ECFL, fv.FV_ENONPHYS, fv.FV_ECFL]
+
+
+def test_tuner_times_the_single_workgroup_variant():
+    """The tuner times every variant, the single-workgroup one included, and the run with its
+    choice equals the oracle bit for bit."""
+    torch = torch_gpu()
+    N = 1024
+    p = O.Problem(dim=1, n=(N,), eq="euler", flux="rusanov", recon="first_order",
+                  integrator="forward_euler", bc=("transmissive",))
+    U0 = fi.sod_state(N)
+    s = solver_for(p)
+    chosen = s.tune(torch.from_numpy(U0).cuda())
+    assert 0 <= chosen < s.num_variants() and s.tile()[1] == chosen
+    R, rt, rs, re = O.evolve(p, U0, 0.2, 0.45)
+    G, gt, gs, ge, st = gpu_evolve(p, U0, 0.2, 0.45, solver=s)
+    assert gs[0] == rs[0] and gt[0] == rt[0]
+    assert_parity(G, R, what=f"sod with tuned variant {chosen}")
