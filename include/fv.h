@@ -160,6 +160,24 @@ fv_status fv_evolve(fv_solver* solver, double* state, int64_t batch, double* t, 
 fv_status fv_advance(fv_solver* solver, double* state, int64_t batch, double* t, double t_end,
                      double cfl, int64_t nsteps, int64_t* steps, int32_t* err);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): fv_advance with the same arguments, semantics and
+ * results (bit for bit), run in a workspace that the library holds in a fixed device array,
+ * one per device, for the life of the process, instead of the solver's workspace. The call
+ * allocates no device or pinned host memory: it launches the tiled stage kernels directly
+ * (no graph, no single-workgroup variant, no kernel timing) and finds the first failing
+ * sample on the device. The batch's workspace (fv_workspace_size) must fit in
+ * fv_noalloc_capacity() bytes (68 MiB: e.g. one 1024^2 Euler sample with SSP-RK3, or 16
+ * samples of 256^2), else FV_ENOMEM before any device work. Every solver on a device shares
+ * that device's array, which keeps the last call's contents (each call initialises what it
+ * reads): calls that overlap in time on one device race and give undefined results. */
+fv_status fv_advance_noalloc(fv_solver* solver, double* state, int64_t batch, double* t,
+                             double t_end, double cfl, int64_t nsteps, int64_t* steps,
+                             int32_t* err);
+
+/* Bytes of the fixed per-device workspace of fv_advance_noalloc. */
+size_t fv_noalloc_capacity(void);
+
 /* Exactly nsteps steps of the fixed size dt for every sample (no clipping). Before each
  * step a sample whose dt * M_b exceeds cfl_bound stops with FV_ECFL; non-physical states
  * stop it with FV_ENONPHYS. err as in fv_evolve. */

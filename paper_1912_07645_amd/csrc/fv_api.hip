@@ -153,6 +153,31 @@ static fv_status validate_grid(const fv_grid* g)
     return FV_OK;
 }
 
+// Workspace of fv_advance_noalloc: Runge--Kutta stage copies and per-sample control words,
+// one copy per device for the life of the process. In host code the array's name stands for
+// no device address: kernels and copies take the address that hipGetSymbolAddress returns for
+// the current device, kept in noalloc_ptr by fv_create.
+constexpr size_t kNoAllocBytes = (size_t)68 << 20;
+static __device__ __align__(256) unsigned char noalloc_scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex noalloc_mu;
+static void* noalloc_ptr[kMaxDevices];
+
+// Resolve the array's address on `device` (current) once; fv_create calls this.
+static fv_status noalloc_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(FV_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_ptr[device]) return FV_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !p)
+        return fail(FV_EDEVICE, std::string("hipGetSymbolAddress(noalloc_scratch): ") + hipGetErrorString(e));
+    noalloc_ptr[device] = p;
+    return FV_OK;
+}
+
 extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32_t flux,
                                int32_t recon, int32_t integrator, fv_solver** out)
 {
@@ -214,6 +239,11 @@ extern "C" fv_status fv_create(const fv_grid* grid, const fv_equation* eq, int32
     if (e != hipSuccess) {
         fv_destroy(s);
         return fail(FV_EDEVICE, std::string("fv_create: ") + hipGetErrorString(e));
+    }
+    st = noalloc_setup(s->device);
+    if (st) {
+        fv_destroy(s);
+        return st;
     }
     if (grid->dim == 1) {
         const SmallKernel* sk = find_small_kernel(eq->kind, recon, flux);
@@ -465,7 +495,7 @@ static void apply_params(StepPlan& p, const CtrlParams& c)
 // has no running sample left, it is dropped from the launches and the graph is captured
 // again, so finished coarse levels stop costing launch slots.
 static fv_status run_steps(fv_solver* s0, std::vector<GroupRun> runs, const CtrlParams& cp,
-                           const std::vector<char>& key0)
+                           const std::vector<char>& key0, bool eager_only = false)
 {
     hipStream_t st = s0->stream;
     const int64_t max_steps = cp.max_steps;
@@ -477,8 +507,8 @@ static fv_status run_steps(fv_solver* s0, std::vector<GroupRun> runs, const Ctrl
     launch_ctrl_begin(p.ctrl, st);
     HIP_TRY(hipGetLastError());
     const int64_t chunk = chunk_steps(max_steps);
-    const bool profile = s0->profile;
-    const bool use_graph = graphs_enabled() && !profile;
+    const bool profile = s0->profile && !eager_only;
+    const bool use_graph = graphs_enabled() && !profile && !eager_only;
     const size_t nst = p.stages.size();
     if (profile) {
         const size_t need = 2 * (size_t)chunk;
@@ -576,10 +606,14 @@ static void key_push(std::vector<char>& k, const T& v)
     k.insert(k.end(), p, p + sizeof(T));
 }
 
+// fixed_ws (with fixed_ws_bytes): run in this device memory instead of the solver's workspace,
+// with the tiled kernels launched eagerly (no graph, no timing events) and the first failing
+// sample found on the device, so that the call allocates nothing.
 static fv_status evolve_common(fv_solver* s, double* state, int64_t batch, double* t,
                                double t_end, double cfl, int64_t max_steps, int64_t* steps,
                                int32_t* err, bool limit_is_error, bool fixed, double fixed_dt,
-                               double cfl_bound)
+                               double cfl_bound, char* fixed_ws = nullptr,
+                               size_t fixed_ws_bytes = 0)
 {
     if (!s) return fail(FV_EINVAL, "solver is NULL");
     if (!state) return fail(FV_EINVAL, "state is NULL");
@@ -601,7 +635,7 @@ static fv_status evolve_common(fv_solver* s, double* state, int64_t batch, doubl
     }();
     if (blocks_per_sample * batch > 0x7fffffffLL) return fail(FV_EINVAL, "launch too large");
     HIP_TRY(hipSetDevice(s->device));
-    if (s->use_small && !s->profile) {
+    if (s->use_small && !s->profile && !fixed_ws) {
         // the single-workgroup time loop: each launch runs every sample up to kSmallChunk
         // steps; launches repeat while samples still run
         constexpr int64_t kSmallChunk = 1 << 16;
@@ -654,12 +688,21 @@ static fv_status evolve_common(fv_solver* s, double* state, int64_t batch, doubl
         return result;
     }
     WsLayout L = ws_layout(s, batch);
-    fv_status st = ensure_workspace(s, L.total);
-    if (st) return st;
+    fv_status st = FV_OK;
+    if (fixed_ws) {
+        if (L.total > fixed_ws_bytes)
+            return fail(FV_ENOMEM, "batch needs " + std::to_string(L.total) +
+                                       " bytes of workspace; the allocation-free call has " +
+                                       std::to_string(fixed_ws_bytes));
+    } else {
+        st = ensure_workspace(s, L.total);
+        if (st) return st;
+    }
     st = stream_enter(s);
     if (st) return st;
+    char* ws = fixed_ws ? fixed_ws : (char*)s->ws;
 
-    std::vector<GroupRun> runs{GroupRun{s, state, batch, fixed ? nullptr : t, steps, err, L, (char*)s->ws}};
+    std::vector<GroupRun> runs{GroupRun{s, state, batch, fixed ? nullptr : t, steps, err, L, ws}};
     const CtrlParams cp{fixed ? 1 : 0, limit_is_error ? 1 : 0, t_end, cfl, fixed_dt, cfl_bound, max_steps};
 
     std::vector<char> key;
@@ -669,11 +712,25 @@ static fv_status evolve_common(fv_solver* s, double* state, int64_t batch, doubl
     key_push(key, cfl_bound); key_push(key, s->ws); key_push(key, s->variant);
     key_push(key, chunk_steps(max_steps));
 
-    st = run_steps(s, runs, cp, key);
+    st = run_steps(s, runs, cp, key, fixed_ws != nullptr);
     if (st) return st;
     fv_status result = FV_OK;
-    st = first_error(s, make_ctrl(runs[0]).err, batch, &result);
-    if (st) return st;
+    if (fixed_ws) {
+        // the first failing sample, found on the device and read into the pinned counters
+        launch_first_error(make_ctrl(runs[0]).err, (int32_t)batch, (int32_t*)(ws + L.count), s->stream);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(s->host_count, ws + L.count, 2 * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (s->host_count[0] != 0) {
+            result = (fv_status)s->host_count[0];
+            g_last_error = "sample " + std::to_string(s->host_count[1]) + " failed with status " +
+                           std::to_string(s->host_count[0]);
+        }
+    } else {
+        st = first_error(s, make_ctrl(runs[0]).err, batch, &result);
+        if (st) return st;
+    }
     st = stream_leave(s);
     if (st) return st;
     return result;
@@ -689,6 +746,25 @@ extern "C" fv_status fv_advance(fv_solver* s, double* state, int64_t batch, doub
                                 double cfl, int64_t nsteps, int64_t* steps, int32_t* err)
 {
     return evolve_common(s, state, batch, t, t_end, cfl, nsteps, steps, err, false, false, 0.0, 0.0);
+}
+
+// ------------------------------------------------------------------ allocation-free stepping
+
+extern "C" size_t fv_noalloc_capacity(void) { return kNoAllocBytes; }
+
+extern "C" fv_status fv_advance_noalloc(fv_solver* s, double* state, int64_t batch, double* t,
+                                        double t_end, double cfl, int64_t nsteps, int64_t* steps,
+                                        int32_t* err)
+{
+    if (!s) return fail(FV_EINVAL, "solver is NULL");
+    void* p = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(noalloc_mu);
+        if (s->device >= 0 && s->device < kMaxDevices) p = noalloc_ptr[s->device];
+    }
+    if (!p) return fail(FV_EDEVICE, "no allocation-free workspace on the solver's device");
+    return evolve_common(s, state, batch, t, t_end, cfl, nsteps, steps, err, false, false, 0.0, 0.0,
+                         (char*)p, kNoAllocBytes);
 }
 
 extern "C" fv_status fv_evolve_fixed_dt(fv_solver* s, double* state, int64_t batch, double dt,

@@ -46,5 +46,7 @@ struct CopyArgs {
 void launch_ctrl_reset(const CtrlArgs& a, hipStream_t s);
 void launch_ctrl_begin(const CtrlArgs& a, hipStream_t s);
 void launch_copy_back(const CopyArgs& a, hipStream_t s);
+// out: device int32[2] = (status of the first failing sample, its index), or (0, -1).
+void launch_first_error(const int32_t* err, int32_t batch, int32_t* out, hipStream_t s);
 
 }  // namespace fvk

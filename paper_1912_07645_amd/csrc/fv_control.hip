@@ -121,6 +121,31 @@ __global__ void copy_back_kernel(const CopyArgs a)
     }
 }
 
+// The status of the first failing sample: out[0] = err[b] and out[1] = b for the smallest b
+// with err[b] != 0, or out[0] = 0 and out[1] = -1 when every sample succeeded. One workgroup.
+__global__ void __launch_bounds__(1024) first_error_kernel(const int32_t* __restrict__ err,
+                                                           int32_t batch, int32_t* __restrict__ out)
+{
+    __shared__ int first;
+    if (threadIdx.x == 0) first = INT32_MAX;
+    __syncthreads();
+    for (int b = threadIdx.x; b < batch; b += blockDim.x)
+        if (err[b] != 0) {
+            atomicMin(&first, b);
+            break;
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        out[0] = (first == INT32_MAX) ? 0 : err[first];
+        out[1] = (first == INT32_MAX) ? -1 : first;
+    }
+}
+
+void launch_first_error(const int32_t* err, int32_t batch, int32_t* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(first_error_kernel, dim3(1), dim3(1024), 0, s, err, batch, out);
+}
+
 void launch_ctrl_reset(const CtrlArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(ctrl_reset_kernel, dim3(64), dim3(256), 0, s, a);

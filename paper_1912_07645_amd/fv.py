@@ -55,6 +55,8 @@ def _load():
         "fv_set_workspace": (i32, [vp, vp, C.c_size_t]),
         "fv_evolve": (i32, [vp, vp, i64, vp, dbl, dbl, i64, vp, vp]),
         "fv_advance": (i32, [vp, vp, i64, vp, dbl, dbl, i64, vp, vp]),
+        "fv_advance_noalloc": (i32, [vp, vp, i64, vp, dbl, dbl, i64, vp, vp]),
+        "fv_noalloc_capacity": (C.c_size_t, []),
         "fv_evolve_fixed_dt": (i32, [vp, vp, i64, dbl, i64, dbl, vp]),
         "fv_evolve_multi": (i32, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(i64), C.POINTER(vp),
                                   dbl, dbl, i64, C.POINTER(vp), C.POINTER(vp)]),
@@ -185,6 +187,18 @@ def fv_advance(solver, state, batch, t, t_end, cfl, nsteps, steps=None, err=None
     if st in (FV_EINVAL, FV_ENOTSUP, FV_ENOMEM, FV_EDEVICE):
         check(st, "fv_advance")
     return st
+
+
+def fv_advance_noalloc(solver, state, batch, t, t_end, cfl, nsteps, steps=None, err=None) -> int:
+    st = lib.fv_advance_noalloc(solver, ptr(state), int(batch), ptr(t), float(t_end), float(cfl),
+                                int(nsteps), ptr(steps), ptr(err))
+    if st in (FV_EINVAL, FV_ENOTSUP, FV_ENOMEM, FV_EDEVICE):
+        check(st, "fv_advance_noalloc")
+    return st
+
+
+def fv_noalloc_capacity() -> int:
+    return lib.fv_noalloc_capacity()
 
 
 def fv_evolve_fixed_dt(solver, state, batch, dt, nsteps, cfl_bound, err=None) -> int:

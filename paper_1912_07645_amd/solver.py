@@ -81,6 +81,14 @@ class Solver:
         self._prepare(B)
         return fv.fv_advance(self.handle, U, B, t, t_end, cfl, nsteps, steps, err)
 
+    def advance_noalloc(self, U, t, t_end, cfl, nsteps, steps=None, err=None) -> int:
+        """fv_advance in the library's fixed per-device workspace: no allocation, no workspace
+        argument (FV_ENOMEM beyond fv.fv_noalloc_capacity() bytes of workspace)."""
+        B = self._check_state(U)
+        _require_gpu_tensor(t, "t", torch.float64)
+        fv.fv_set_stream(self.handle, torch.cuda.current_stream(self.device).cuda_stream)
+        return fv.fv_advance_noalloc(self.handle, U, B, t, t_end, cfl, nsteps, steps, err)
+
     def evolve_fixed_dt(self, U, dt, nsteps, cfl_bound=1.0, err=None) -> int:
         B = self._check_state(U)
         self._prepare(B)
