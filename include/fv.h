@@ -326,8 +326,9 @@ fv_status fv_structure_shell(const fv_solver* solver, const double* state, int64
  * Section 2.1). The forward map is nsteps SSP Runge--Kutta steps of size dt; the adjoint is
  * the exact transpose of its linearisation, with the forward pass's branch choices (the
  * larger Rusanov wave speed, ties to the right state; the minmod argument selected; the
- * derivative of |u| at 0 taken as 0). Supported: the Euler equations in 1D and 2D with the
- * Rusanov flux and first-order or MUSCL-minmod reconstruction (FV_ENOTSUP otherwise).
+ * derivative of |u| at 0 taken as 0). Supported: the Euler equations in 1D and 2D on periodic
+ * grids with the Rusanov flux and first-order or MUSCL-minmod reconstruction (FV_ENOTSUP
+ * otherwise, also for a transmissive axis).
  *
  * fv_adjoint_create allocates, for `batch` samples of the solver's grid, ceil(nsteps/every)
  * checkpoint states, every * stages + 1 segment states and three adjoint states (device
@@ -361,6 +362,17 @@ fv_status fv_adjoint_forward(fv_adjoint* adj, const double* state0, double* stat
  * shape, not modified), recomputing each checkpoint segment. Needs a completed
  * fv_adjoint_forward. */
 fv_status fv_adjoint_backward(fv_adjoint* adj, const double* dQ_dUT, double* dQ_dU0);
+
+/* Branch signature (a diagnostic for finite-difference checks of the adjoint, whose map is only
+ * piecewise smooth): while sig (device uint64[batch], caller-owned and cleared by the caller)
+ * is set, every fv_adjoint_backward adds to sig[b], modulo 2^64, one hashed term per face and
+ * reverse Runge--Kutta stage of sample b. The term hashes the stage's place in the sweep, the
+ * face, and the branches the forward pass took there: the minmod branch of both face values
+ * of every field, the side of the larger Rusanov speed, the sign of the selected normal
+ * velocity. Two trajectories that take the same branches everywhere give equal signatures;
+ * one differing branch changes the signature except with probability about 2^-64. Both
+ * checkpointing schedules give the same signature. sig = NULL turns it off. */
+fv_status fv_adjoint_set_signature(fv_adjoint* adj, uint64_t* sig);
 
 fv_status fv_adjoint_destroy(fv_adjoint* adj);
 

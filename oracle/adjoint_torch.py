@@ -13,7 +13,8 @@ The map theta -> Q is the definition of what the adjoint differentiates:
 Every operation is written with the same operands and parentheses as the C oracle, so the
 forward values equal it; autograd then applies the chain rule step by step. Kinks take the
 branch the forward comparison selected (torch.where routes the gradient to the chosen
-operand; d|u|/du = 0 at u = 0). Memory is bounded by checkpointing every time step.
+operand; d|u|/du = 0 at u = 0). The reverse sweep keeps every step's state and rebuilds one
+step's graph at a time, so memory is the trajectory plus one step.
 """
 from __future__ import annotations
 
@@ -21,7 +22,6 @@ import math
 
 import numpy as np
 import torch
-from torch.utils.checkpoint import checkpoint
 
 GAMMA = 1.4
 
@@ -31,15 +31,22 @@ class _IEEESqrt(torch.autograd.Function):
     sqrt is not correctly rounded, and the forward values must equal the C oracle's."""
 
     @staticmethod
-    def forward(ctx, x):
-        y = torch.from_numpy(np.sqrt(x.detach().numpy()))
-        ctx.save_for_backward(y)
-        return y
+    def forward(x):
+        return torch.from_numpy(np.sqrt(x.detach().numpy()))
 
     @staticmethod
     def backward(ctx, g):
         (y,) = ctx.saved_tensors
         return g / (2.0 * y)
+
+    @staticmethod
+    def jvp(ctx, dx):
+        return dx / (2.0 * ctx.y_fwd)
+
+    @staticmethod
+    def setup_context(ctx, inputs, output):
+        ctx.save_for_backward(output)
+        ctx.y_fwd = output.detach()
 
 
 def _sqrt(x):
@@ -117,16 +124,93 @@ def ssprk3_step(U, dt, inv_dx, recon="muscl_minmod", integrator="ssprk3"):
     return Us
 
 
+def _reverse_steps(U, lam, dt, inv_dx, nsteps, recon, integrator):
+    """(dU_T/dU)^T lam through nsteps steps from the tensor U: the states of every step are
+    kept (no graph), then each step's graph is rebuilt from its state and differentiated,
+    last step first (the chain rule of the step map, one step in memory at a time)."""
+    states = [U]
+    with torch.no_grad():
+        for _ in range(nsteps - 1):
+            states.append(ssprk3_step(states[-1], dt, inv_dx, recon, integrator))
+    for Un in reversed(states):
+        x = Un.detach().requires_grad_(True)
+        y = ssprk3_step(x, dt, inv_dx, recon, integrator)
+        (lam,) = torch.autograd.grad(y, x, grad_outputs=lam)
+    return lam
+
+
 def vjp_steps(U0, lamT, n, dt, nsteps, recon="muscl_minmod", integrator="ssprk3"):
     """dQ/dU0 for Q = <lamT, U_T>, U_T = nsteps steps from U0 (numpy [B][4][1][n][n])."""
-    U = torch.tensor(np.asarray(U0)[:, :, 0], dtype=torch.float64, requires_grad=True)
-    V = U
-    for _ in range(nsteps):
-        V = checkpoint(ssprk3_step, V, dt, (float(n), float(n)), recon, integrator,
-                       use_reentrant=False)
+    U = torch.tensor(np.asarray(U0)[:, :, 0], dtype=torch.float64)
     lam = torch.tensor(np.asarray(lamT)[:, :, 0], dtype=torch.float64)
-    (V * lam).sum().backward()
-    return U.grad.numpy()[:, :, None]
+    return _reverse_steps(U, lam, dt, (float(n), float(n)), nsteps, recon,
+                          integrator).numpy()[:, :, None]
+
+
+def jvp_steps(U0, v, n, dt, nsteps, recon="muscl_minmod", integrator="ssprk3"):
+    """(dU_T/dU0) v by forward-mode differentiation (dual numbers through the same forward
+    operations): the tangent that the reverse mode of vjp_steps transposes."""
+    import torch.autograd.forward_ad as fwAD
+    with fwAD.dual_level():
+        U = fwAD.make_dual(torch.tensor(np.asarray(U0)[:, :, 0], dtype=torch.float64),
+                           torch.tensor(np.asarray(v)[:, :, 0], dtype=torch.float64))
+        for _ in range(nsteps):
+            U = ssprk3_step(U, dt, (float(n), float(n)), recon, integrator)
+        t = fwAD.unpack_dual(U).tangent
+    return t.numpy()[:, :, None]
+
+
+def stage_branches(U, inv_dx):
+    """The branches the right-hand side of eq. (2.1) takes at state U (MUSCL-minmod + Rusanov),
+    per axis: the minmod branch of every cell and field (0: zero, 1: the backward difference,
+    2: the forward difference, as _minmod chooses), the side of the larger Rusanov speed of
+    every face (1: left) and the sign of the normal velocity on that side."""
+    out = []
+    for d in (0, 1):
+        ax = 3 if d == 0 else 2
+        a = U - torch.roll(U, 1, dims=ax)
+        b = torch.roll(U, -1, dims=ax) - U
+        both_pos = (a > 0) & (b > 0)
+        both_neg = (a < 0) & (b < 0)
+        mm = torch.where(both_pos, torch.where(a < b, 1, 2),
+                         torch.where(both_neg, torch.where(a > b, 1, 2), 0))
+        sigma = _minmod(a, b)
+        UL = U + (0.5 * sigma)
+        UR = torch.roll(U - (0.5 * sigma), -1, dims=ax)
+        pl, pr = _prim(UL), _prim(UR)
+        ul = pl[1] if d == 0 else pl[2]
+        ur = pr[1] if d == 0 else pr[2]
+        left = (torch.abs(ul) + pl[4]) > (torch.abs(ur) + pr[4])
+        sign = torch.sign(torch.where(left, ul, ur))
+        out.append((mm.to(torch.int8), left.to(torch.int8), sign.to(torch.int8)))
+    return out
+
+
+def forward_with_branches(U0, n, dt, nsteps):
+    """The SSP-RK3 forward run (numpy [B][4][1][n][n]) -> (U_T, branches), branches a list over
+    (step, stage) of stage_branches at the stage's input state."""
+    rec = []
+    with torch.no_grad():
+        U = torch.tensor(np.asarray(U0)[:, :, 0], dtype=torch.float64)
+        for _ in range(nsteps):
+            Un = U
+            Us = U
+            for beta in BETAS["ssprk3"]:
+                rec.append(stage_branches(Us, (float(n), float(n))))
+                Us = Un + (beta * ((Us - Un) + (dt * rhs(Us, (float(n), float(n))))))
+            U = Us
+    return U.numpy()[:, :, None], rec
+
+
+def branch_flips(rec_a, rec_b, sample):
+    """Number of (stage, axis, cell or face, field) branch choices of `sample` that differ
+    between two recorded runs."""
+    n = 0
+    for sa, sb in zip(rec_a, rec_b):
+        for xa, xb in zip(sa, sb):
+            for ya, yb in zip(xa, xb):
+                n += int((ya[sample] != yb[sample]).sum())
+    return n
 
 
 def initial_state(c, phi, n, a=0.01):
@@ -177,10 +261,15 @@ def qoi_and_gradient(c, phi, n, dt, nsteps, U0_values=None):
         exact = torch.tensor(np.asarray(U0_values)[:, :, 0], dtype=torch.float64)
         U = U + (exact - U).detach()
     inv_dx = (float(n), float(n))
-    for _ in range(nsteps):
-        U = checkpoint(ssprk3_step, U, dt, inv_dx, use_reentrant=False)
-    Q = qoi(U, n)
-    Q.sum().backward()
+    with torch.no_grad():
+        UT = U.detach()
+        for _ in range(nsteps):
+            UT = ssprk3_step(UT, dt, inv_dx)
+    x = UT.requires_grad_(True)
+    Q = qoi(x, n)
+    (lamT,) = torch.autograd.grad(Q.sum(), x)
+    lam0 = _reverse_steps(U.detach(), lamT, dt, inv_dx, nsteps, "muscl_minmod", "ssprk3")
+    U.backward(lam0)
     return Q.detach().numpy(), ct.grad.numpy(), pt.grad.numpy()
 
 

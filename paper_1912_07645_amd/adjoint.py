@@ -36,6 +36,8 @@ class Adjoint:
             self.every = None
             self.handle = fv.fv_adjoint_create_binomial(solver.handle, batch, nsteps, dt,
                                                         self.snapshots, cfl_bound)
+        # forward runs so far: the checkpoints (and the backward sweep) belong to the last one
+        self.generation = 0
 
     def recomputed_steps(self) -> int:
         """Forward steps the last reverse sweep ran to recompute states."""
@@ -59,6 +61,7 @@ class Adjoint:
         self._stream()
         UT = torch.empty_like(U0)
         fv.fv_adjoint_forward(self.handle, U0, UT)
+        self.generation += 1
         return UT
 
     def backward(self, dQ_dUT):
@@ -67,6 +70,20 @@ class Adjoint:
         g0 = torch.empty_like(dQ_dUT)
         fv.fv_adjoint_backward(self.handle, dQ_dUT.contiguous(), g0)
         return g0
+
+    def branch_signature(self, U0):
+        """(sig, U_T): the signature of the branches the forward run from U0 takes
+        (fv_adjoint_set_signature; int64 [batch], the bits of the uint64 sums) and the run's
+        final state. Runs the forward pass and one reverse sweep."""
+        B = self.solver._check_state(U0)
+        sig = torch.zeros(B, dtype=torch.int64, device=U0.device)
+        UT = self.forward(U0)
+        fv.fv_adjoint_set_signature(self.handle, sig)
+        try:
+            self.backward(torch.zeros_like(U0))
+        finally:
+            fv.fv_adjoint_set_signature(self.handle, None)
+        return sig, UT
 
 
 def band_rows(n: int, centre: float = 0.5, half_width: float = 0.1):
@@ -108,6 +125,7 @@ class LineInitialDataQoI(torch.autograd.Function):
         UT = adjoint.forward(U0)
         Q, _ = kinetic_energy(adjoint.solver, UT, j0, j1)
         ctx.adjoint, ctx.j0, ctx.j1 = adjoint, j0, j1
+        ctx.generation = adjoint.generation
         ctx.save_for_backward(UT, D, E)
         return Q
 
@@ -115,6 +133,10 @@ class LineInitialDataQoI(torch.autograd.Function):
     def backward(ctx, gQ):
         UT, D, E = ctx.saved_tensors
         adj = ctx.adjoint
+        if adj.generation != ctx.generation:
+            raise RuntimeError("the Adjoint handle ran another forward pass after this graph was "
+                               "built: its checkpoints belong to that run; use one Adjoint per "
+                               "pending backward")
         _, dQ_dUT = kinetic_energy(adj.solver, UT, ctx.j0, ctx.j1, seed=gQ.contiguous())
         lam0 = adj.backward(dQ_dUT)
         g = line_vjp(adj.solver, lam0, D, E)

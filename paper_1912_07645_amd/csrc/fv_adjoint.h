@@ -29,6 +29,10 @@ struct AdjArgs {
     double dt;
     int64_t nblocks;
     Phys ph;
+    // branch signature (diagnostic; null: off): sig[sample] += one hashed term per face of the
+    // launch, from salt (the launch), the face and its branch choices, modulo 2^64
+    unsigned long long* sig;
+    unsigned long long salt;
 };
 
 struct AdjKernel {

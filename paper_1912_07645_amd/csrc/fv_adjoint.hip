@@ -78,6 +78,14 @@ __device__ __forceinline__ int minmod_code(double a, double b)
     return 0;
 }
 
+// SplitMix64's finaliser (Steele, Lea and Flood 2014): hashes the branch-signature terms.
+__device__ __forceinline__ unsigned long long sig_mix(unsigned long long z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 template <int DIM, int RECON, int BX, int BY, int NT>
 struct AdjTile {
     static constexpr int NF = DIM + 2;
@@ -111,6 +119,7 @@ adjoint_stage_kernel(const AdjArgs a)
     __shared__ double sl[NF * LC];
     __shared__ double sg[2 * NF * MAXF];   // g_L, g_R per face of the axis in hand
     __shared__ int scode[MAXF];            // minmod codes, 2 bits per component and side
+    __shared__ unsigned long long ssig;    // the workgroup's branch-signature sum
 
     const int64_t blk = xcd_remap(blockIdx.x, a.nblocks);
     const int32_t sample = (int32_t)(blk / a.ntiles);
@@ -177,6 +186,7 @@ adjoint_stage_kernel(const AdjArgs a)
     for (int k = 0; k < T::CPT; ++k)
 #pragma unroll
         for (int q = 0; q < NF; ++q) jt[k][q] = 0.0;
+    unsigned long long hsig = 0ull;   // this thread's signature terms (faces it owns)
 #pragma unroll
     for (int nd = 0; nd < DIM; ++nd) {
         const int nfaces = (nd == 0) ? NFX : NFY;
@@ -237,6 +247,19 @@ adjoint_stage_kernel(const AdjArgs a)
                 sg[(2 * q + 1) * MAXF + f] = gR;
             }
             scode[f] = codes;
+            if (a.sig) {
+                // each face once: by the tile of its right cell, inside the grid
+                const int32_t gx = x0 + fx, gy = (DIM >= 2) ? y0 + fy : 0;
+                const bool own = (nd == 0) ? (fx >= 0 && fx < BX) : (fy >= 0 && fy < BY);
+                if (own && gx < nx && gy < ny) {
+                    const double un = selL ? pick<DIM>(pl.u, nd) : pick<DIM>(pr.u, nd);
+                    const unsigned long long sgn = (un > 0.0) ? 2ull : ((un < 0.0) ? 0ull : 1ull);
+                    const unsigned long long code = (unsigned long long)(unsigned)codes |
+                                                    ((selL ? 1ull : 0ull) << 32) | (sgn << 33);
+                    const unsigned long long key = ((unsigned long long)(gy * nx + gx) << 2) | nd;
+                    hsig += sig_mix(a.salt ^ sig_mix(key * 0x9E3779B97F4A7C15ull + code));
+                }
+            }
         }
         __syncthreads();
 
@@ -286,6 +309,13 @@ adjoint_stage_kernel(const AdjArgs a)
             }
         }
         if (nd + 1 < DIM) __syncthreads();   // the next axis overwrites sg
+    }
+    if (a.sig) {   // uniform over the launch
+        if (threadIdx.x == 0) ssig = 0ull;
+        __syncthreads();
+        atomicAdd(&ssig, hsig);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(a.sig + sample, ssig);
     }
 
     // the reverse stage combination

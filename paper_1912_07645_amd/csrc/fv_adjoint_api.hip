@@ -47,6 +47,8 @@ struct fv_adjoint {
     unsigned long long* mbits = nullptr;
     int32_t* bad = nullptr;
     bool forward_done = false;
+    unsigned long long* sig = nullptr;   // caller's branch-signature sums (diagnostic)
+    unsigned long long rev_launch = 0;   // reverse stage launches of the current sweep
 };
 
 static __global__ void adj_init_kernel(double* dt_arr, int32_t* active, unsigned long long* mbits,
@@ -119,6 +121,10 @@ static fv_status adjoint_create(fv_solver* s, int64_t batch, int64_t nsteps, dou
     if (!ak)
         return fail(FV_ENOTSUP, "the adjoint covers the Euler equations in 1D/2D with the Rusanov "
                                 "flux and first-order or MUSCL-minmod reconstruction");
+    for (int k = 0; k < s->grid.dim; ++k)
+        if (s->grid.bc[k] != FV_BC_PERIODIC)
+            return fail(FV_ENOTSUP, "the adjoint covers periodic grids only (a transmissive "
+                                    "boundary face has terms the reverse stage does not add)");
     if (binomial) {
         if (snapshots < 0) return fail(FV_EINVAL, "snapshots must be >= 0");
         snapshots = std::min(snapshots, nsteps);
@@ -189,6 +195,13 @@ extern "C" fv_status fv_adjoint_recomputed_steps(const fv_adjoint* a, int64_t* s
 {
     if (!a || !steps) return fail(FV_EINVAL, "NULL argument");
     *steps = a->recomputed;
+    return FV_OK;
+}
+
+extern "C" fv_status fv_adjoint_set_signature(fv_adjoint* a, uint64_t* sig)
+{
+    if (!a) return fail(FV_EINVAL, "adjoint is NULL");
+    a->sig = (unsigned long long*)sig;
     return FV_OK;
 }
 
@@ -293,6 +306,8 @@ static fv_status reverse_stage(fv_adjoint* a, const double* U, const double* lam
     g.dt = a->dt;
     g.nblocks = (int64_t)g.ntiles * a->batch;
     g.ph = s->ph;
+    g.sig = a->sig;
+    g.salt = 0x2545F4914F6CDD1Dull * (++a->rev_launch);
     a->ak->launch(g, s->stream);
     return FV_OK;
 }
@@ -432,6 +447,7 @@ extern "C" fv_status fv_adjoint_backward(fv_adjoint* a, const double* dQ_dUT, do
     int cur = 0;   // lam[cur] holds dQ/dU^{n+1}
     HIP_TRY(hipMemcpyAsync(a->lam[cur], dQ_dUT, sb, hipMemcpyDeviceToDevice, st));
     a->recomputed = 0;
+    a->rev_launch = 0;   // both schedules reverse the steps last to first: same salts
     if (a->binomial) {
         revolve(a, 0, a->nsteps, a->snapshots, a->ckpt, cur);
         HIP_TRY(hipGetLastError());

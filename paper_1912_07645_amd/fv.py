@@ -82,6 +82,7 @@ def _load():
         "fv_adjoint_forward": (i32, [vp, vp, vp]),
         "fv_adjoint_backward": (i32, [vp, vp, vp]),
         "fv_adjoint_destroy": (i32, [vp]),
+        "fv_adjoint_set_signature": (i32, [vp, vp]),
         "fv_qoi_kinetic_energy": (i32, [vp, vp, i64, i64, i64, vp, vp, vp]),
         "fv_line_vjp": (i32, [vp, vp, vp, vp, i32, i64, vp]),
         "fv_profile_enable": (i32, [vp, i32]),
@@ -333,6 +334,10 @@ def fv_adjoint_forward(adj, state0, stateT) -> None:
 
 def fv_adjoint_backward(adj, dQ_dUT, dQ_dU0) -> None:
     check(lib.fv_adjoint_backward(adj, ptr(dQ_dUT), ptr(dQ_dU0)), "fv_adjoint_backward")
+
+
+def fv_adjoint_set_signature(adj, sig) -> None:
+    check(lib.fv_adjoint_set_signature(adj, ptr(sig)), "fv_adjoint_set_signature")
 
 
 def fv_adjoint_destroy(adj) -> None:

@@ -83,3 +83,69 @@ def test_initial_data_jacobian_tables_against_finite_differences():
         fd = (fi.kh2d_state(n, cp, pp) - fi.kh2d_state(n, cm, pm)) / (2 * eps)
         an = D * E[:, None, None, None, :, k]
         assert np.abs(fd - an).max() <= 1e-6 * np.abs(an).max()
+
+
+@pytest.mark.parametrize("recon,integ", [("muscl_minmod", "ssprk3"), ("first_order", "forward_euler"),
+                                         ("muscl_minmod", "ssprk2")])
+def test_reverse_mode_is_the_transpose_of_forward_mode(recon, integ):
+    """Dot-product test: <lam, J v> from forward-mode differentiation (dual numbers) equals
+    <J^T lam, v> from the reverse mode that the gradient oracle uses, for random v and lam,
+    to rounding (the two modes evaluate different formulas for the same linear map)."""
+    n, steps = 16, 4
+    U0 = fi.random_smooth_state(3, (1, n, n), 2, batch=2)
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal(U0.shape)
+    lam = rng.standard_normal(U0.shape)
+    p = _problem(n, recon, integ)
+    M, _ = O.max_speed(p, U0[0])
+    dt = 0.4 / M
+    Jv = AT.jvp_steps(U0, v, n, dt, steps, recon, integ)
+    JTl = AT.vjp_steps(U0, lam, n, dt, steps, recon, integ)
+    for b in range(2):
+        a, c = (lam[b] * Jv[b]).sum(), (JTl[b] * v[b]).sum()
+        scale = np.abs(lam[b] * Jv[b]).sum()
+        assert abs(a - c) <= 1e-13 * scale, (b, a, c)
+
+
+def test_finite_difference_errors_come_with_branch_flips():
+    """Kink audit of the gradient oracle against central differences (eps = 1e-6) of the forward
+    run (which equals the C oracle bit for bit): the discrete map is only piecewise smooth
+    (minmod branches, the larger Rusanov speed, |u|), so a difference quotient whose two runs
+    take different branches somewhere need not approach the derivative. Every component whose
+    two runs take the same branches everywhere agrees with the gradient to 1e-6 of the gradient
+    norm (what remains is the rounding of the difference quotient); larger disagreements occur
+    only where a branch flipped."""
+    n, steps, eps = 32, 20, 1e-6
+    c, phi = fi.kh_coefficients(1915, [0, 1])
+    U0 = fi.kh2d_state(n, c, phi)
+    p = _problem(n)
+    M, _ = O.max_speed(p, U0[0])
+    dt = 0.4 / M
+    _, gc, gp = AT.qoi_and_gradient(c, phi, n, dt, steps, U0_values=U0)
+    g = np.concatenate([gc, gp], axis=1)
+    import torch
+    fd = np.zeros_like(g)
+    flips = np.zeros(g.shape, dtype=int)
+    for k in range(20):
+        cp, pp, cm, pm = c.copy(), phi.copy(), c.copy(), phi.copy()
+        if k < 10:
+            cp[:, k] += eps
+            cm[:, k] -= eps
+        else:
+            pp[:, k - 10] += eps
+            pm[:, k - 10] -= eps
+        Up, rp = AT.forward_with_branches(fi.kh2d_state(n, cp, pp), n, dt, steps)
+        Um, rm = AT.forward_with_branches(fi.kh2d_state(n, cm, pm), n, dt, steps)
+        Qp = AT.qoi(torch.from_numpy(Up[:, :, 0]), n).numpy()
+        Qm = AT.qoi(torch.from_numpy(Um[:, :, 0]), n).numpy()
+        fd[:, k] = (Qp - Qm) / (2 * eps)
+        for b in range(2):
+            flips[b, k] = AT.branch_flips(rp, rm, b)
+    err = np.abs(g - fd) / np.linalg.norm(fd, axis=1, keepdims=True)
+    smooth = flips == 0
+    assert smooth.sum() >= 30, smooth.sum()          # most pairs cross no switch at this size
+    assert err[smooth].max() <= 1e-6, err[smooth].max()
+    assert np.all(smooth | (err <= 1e-6) | (flips > 0))
+    print("kink audit 32^2 x 20: %d of 40 components without a flip, max error %.1e; "
+          "flipped components' errors %s" % (smooth.sum(), err[smooth].max(),
+                                             np.array2string(err[~smooth], precision=1)))
