@@ -11,7 +11,7 @@ state already resident in HBM), the roofline of the dominant kernel (the stage k
 timed with HIP events on the library's stream over its own launches) and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh2d_ec4|kh3d|mc|sod|swe2d|mhd2d]
+    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh2d_ec4|kh3d|mc|sod|swe2d|mhd2d|mlmc|adjoint|halo]
     python bench.py --copy-calibration     # plain copy of known size, for rocprof counters
 """
 from __future__ import annotations
@@ -369,6 +369,85 @@ def functionals(s, U, cells, B):
     return out
 
 
+def run_halo(a):
+    """Split-buffer halo exchange (one GPU emulating the subdomains of several): the 1024^2
+    Kelvin--Helmholtz run split along x, along y and both ways, and the 512^3 run split along
+    z. Per split: the step time with the interior updated while the halo copies run
+    (overlap), with the exchange before the whole update (serial), the unsplit step time on
+    the same tile kernel, and the copies' own device time per step (events on the copy stream,
+    serial mode), from which the fraction of copy time the overlap hides follows."""
+    import numpy as np
+    import torch
+    import fv_inputs as fi
+    from paper_1912_07645_amd import Solver
+    from paper_1912_07645_amd.decomp import Decomposition
+
+    dev = torch.device("cuda:0")
+    out = {"metric": "split-buffer step time (ms) and hidden fraction of halo-copy time",
+           "n_gpus": 1, "data": "synthetic", "dtype": "f64", "cases": []}
+
+    def timed(fn, reps=3):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        return best
+
+    for dim, n, splits, K in ((2, 1024, ((2, 1), (1, 2), (2, 2)), 320), (3, 512, ((1, 1, 2),), 16)):
+        if dim == 2:
+            c, phi = fi.kh_coefficients(1912, [0])
+            U0 = fi.kh2d_state(n, c, phi)
+        else:
+            cx, px, cz, pz = fi.kh3d_coefficients(1914, [0])
+            U0 = fi.kh3d_state(n, cx, px, cz, pz)
+        s = Solver(dim=dim, n=(n,) * dim, eq="euler", flux="hllc", recon="weno3",
+                   integrator="ssprk3", device=dev)
+        want = (16, 15, 1) if dim == 2 else (8, 8, 4)     # the tile of the split-run kernel
+        for v in range(s.num_variants()):
+            s.set_variant(v)
+            if tuple(s.tile()[0]) == want:
+                break
+        U = torch.from_numpy(U0).to(dev)
+        t = torch.zeros(1, dtype=torch.float64, device=dev)
+        s.advance(U, t, 1e9, 0.4, 2)
+        unsplit = timed(lambda: s.advance(U, t, 1e9, 0.4, K)) / K
+        for parts in splits:
+            d = Decomposition(s, parts, 1)
+            d.scatter(U)
+            td = torch.zeros(1, dtype=torch.float64, device=dev)
+            info = d.info()
+            case = {"workload": f"kh{dim}d_{n}^{dim}_weno3_hllc_ssprk3", "parts": list(parts),
+                    "messages_per_stage": info["messages"],
+                    "halo_bytes_per_stage": info["halo_bytes_per_stage"],
+                    "interior_tiles": info["interior_tiles"], "shell_tiles": info["shell_tiles"],
+                    "unsplit_ms_per_step": unsplit * 1e3}
+            for dma in (False, True):
+                key = "dma" if dma else "copy_kernels"
+                d.advance(td, 1e9, 0.4, 16, overlap=True, dma=dma)
+                ov = timed(lambda: d.advance(td, 1e9, 0.4, K, overlap=True, dma=dma)) / K
+                d.advance(td, 1e9, 0.4, 16, overlap=False, dma=dma)
+                se = timed(lambda: d.advance(td, 1e9, 0.4, K, overlap=False, dma=dma)) / K
+                d.profile(True)
+                d.advance(td, 1e9, 0.4, 8, overlap=False, dma=dma)
+                step_ms, copy_ms, nprof = d.profile_read()
+                d.profile(False)
+                copy = copy_ms / nprof * 1e-3
+                case[key] = {"overlap_ms_per_step": ov * 1e3, "serial_ms_per_step": se * 1e3,
+                             "copy_ms_per_step": copy * 1e3,
+                             "hidden_copy_fraction": max(0.0, min(1.0, (se - ov) / copy)) if copy > 0 else None,
+                             "overlap_over_unsplit": ov / unsplit}
+            out["cases"].append(case)
+            del d
+            torch.cuda.empty_cache()
+        del s, U
+        torch.cuda.empty_cache()
+    print(json.dumps(out))
+
+
 def per_sample_rate(s, U, cfl, K, B1):
     """The same kernels with one sample per launch (the unbatched way), over B1 samples."""
     import torch
@@ -391,7 +470,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="kh2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="kh2d", choices=sorted(WORKLOADS) + ["halo"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="kh2d only: skip the short batched-MC and adjoint measurements")
@@ -415,6 +494,9 @@ def main():
         return
     if a.workload == "adjoint":
         print(json.dumps(run_adjoint(a, WORKLOADS["adjoint"])))
+        return
+    if a.workload == "halo":
+        run_halo(a)
         return
 
     out = measure(a, dict(WORKLOADS[a.workload]))

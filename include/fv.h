@@ -393,6 +393,65 @@ fv_status fv_qoi_kinetic_energy(fv_solver* solver, const double* state, int64_t 
 fv_status fv_line_vjp(fv_solver* solver, const double* lambda0, const double* dU_dline,
                       const double* dline_dtheta, int32_t ntheta, int64_t batch, double* out);
 
+/* ------------------------------------------------------------------ split-buffer decomposition */
+
+/* Domain decomposition of one solver's grid into parts[0] x parts[1] x parts[2] equal
+ * subdomains with their own state arrays on this device, advanced with a halo exchange every
+ * Runge--Kutta stage: the communication of a multi-GPU run (Section 2.1: the exchange and the
+ * compactification of the boundary data are overlapped with the computation of the inner
+ * domain; Section 3.1: splits along x, along y, along both), emulated with device-to-device
+ * copies. Each subdomain stores G ghost layers (2 for MUSCL and WENO3) on every split axis.
+ * Each stage packs the G owned layers next to every face of every subdomain into one
+ * contiguous message per (subdomain, split axis, side). It copies each message on a second
+ * stream into a receive buffer and unpacks it into the neighbour's ghost layers. Results are
+ * bit for bit those of the unsplit solver (the per-cell arithmetic is the same, and the
+ * maximum wave speed is merged exactly over the subdomains).
+ *
+ * fv_decomp_create: parts[k] >= 1 must divide n[k], parts[k] = 1 beyond the grid's dimension,
+ * at most 8 subdomains, split axes periodic with at least 2 G cells per subdomain; the SSP-RK2 or
+ * SSP-RK3 stepper; the Euler equations with WENO3 + HLLC (2D, 3D) or MUSCL + HLL or MUSCL +
+ * Rusanov (2D) (FV_ENOTSUP otherwise, FV_EINVAL for bad sizes). It allocates the subdomain
+ * arrays (cleared) for `batch` samples and the message buffers. The handle uses the solver's
+ * stream and must not outlive the solver. */
+typedef struct fv_decomp fv_decomp;  /* opaque, library-owned */
+fv_status fv_decomp_create(fv_solver* solver, const int32_t* parts, int64_t batch,
+                           fv_decomp** out);
+
+/* Copy a whole-grid state (device double[batch][fields][cells]) into the subdomains' owned
+ * cells (scatter), or the owned cells back into a whole-grid state (gather). Stream-ordered. */
+fv_status fv_decomp_scatter(fv_decomp* d, const double* state);
+fv_status fv_decomp_gather(fv_decomp* d, double* state);
+
+/* fv_advance on the subdomains: at most nsteps steps per sample, each with dt = cfl / M_b and
+ * the last clipped at t_end (t: device double[batch], in/out; steps: device int64[batch] out,
+ * err: device int32[batch] out, both may be NULL). mode is FV_DECOMP_OVERLAP and/or
+ * FV_DECOMP_DMA, or 0. With 0, every stage exchanges the halos, then updates every tile.
+ * FV_DECOMP_OVERLAP: every stage packs and starts the copies, then updates the interior tiles
+ * (whose reads stay in owned cells) on the solver's stream, while the copy stream carries out
+ * the copies, the unpacking and the update of the boundary shell; the next stage waits for
+ * both. FV_DECOMP_DMA: the copies run on the DMA engines (hipMemcpyDeviceToDeviceNoCU), as
+ * transfers between GPUs would, instead of copy kernels on the compute units. FV_EINVAL for
+ * any other mode. Returns FV_OK or the first failing sample's status, after the device has
+ * finished. */
+enum { FV_DECOMP_OVERLAP = 1, FV_DECOMP_DMA = 2 };
+fv_status fv_decomp_advance(fv_decomp* d, double* t, double t_end, double cfl, int64_t nsteps,
+                            int64_t* steps, int32_t* err, int32_t mode);
+
+/* Timing: while enabled, fv_decomp_advance records events around every whole step (compute
+ * stream) and around every stage's copies (copy stream). fv_decomp_profile_read returns their
+ * accumulated durations in milliseconds and the number of timed steps (outputs may be NULL);
+ * enabling or disabling resets them. */
+fv_status fv_decomp_profile_enable(fv_decomp* d, int32_t on);
+fv_status fv_decomp_profile_read(const fv_decomp* d, double* step_ms, double* copy_ms,
+                                 int64_t* steps);
+
+/* Layout facts (outputs may be NULL): subdomains, messages per stage, bytes of all messages of
+ * one stage, tiles per subdomain in the interior box and in the boundary shell. */
+fv_status fv_decomp_info(const fv_decomp* d, int32_t* nsub, int32_t* messages,
+                         int64_t* halo_bytes, int32_t* interior_tiles, int32_t* shell_tiles);
+
+fv_status fv_decomp_destroy(fv_decomp* d);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Human-readable description of the last failure in this thread ("" if none). Valid until

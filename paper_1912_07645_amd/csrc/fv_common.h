@@ -45,6 +45,15 @@ struct Group {
     int32_t batch;
     int64_t block0;            // first block of this group in a multi-group launch
     Phys ph;
+    // Split-buffer subdomains (the halo-layout kernels only): the array holds the owned cells
+    // n[k] at offset off[k] inside an extent pn[k] per axis (cells = pn[0] pn[1] pn[2]); on the
+    // axes of hmask (bit k) the ghost layers are stored in the array, filled by a halo
+    // exchange, instead of wrapped. The launch covers the tiles tlo[k] + [0, tcnt[k]).
+    int32_t pn[3];
+    int32_t off[3];
+    int32_t hmask;
+    int32_t tlo[3];
+    int32_t tcnt[3];
 };
 
 constexpr int kMaxGroups = 8;

@@ -45,6 +45,20 @@ __device__ __forceinline__ int32_t wrap_index(int32_t i, int32_t n, int32_t bc)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// Ghost-cell index map of a split-buffer subdomain along one axis (array coordinates): an
+// axis whose ghosts are stored in the array (halo) reads them there, clamped to the array (a
+// ragged last tile reaches past the halo only for cells it does not update); any other axis
+// wraps or clamps as on a whole grid.
+__device__ __forceinline__ int32_t halo_index(int32_t i, int32_t n, int32_t bc, int32_t off,
+                                              int32_t pn, bool halo)
+{
+    if (halo) {
+        const int32_t a = i + off;
+        return a < 0 ? 0 : (a >= pn ? pn - 1 : a);
+    }
+    return wrap_index(i, n, bc) + off;
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs; remap so that each XCD receives a
 // contiguous range of tiles and halo re-reads of neighbouring tiles hit its own L2.
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks)
@@ -303,7 +317,11 @@ __device__ __forceinline__ int find_group(const Group* g, int ngroups, int64_t b
 template <int EQ, int FLUX, int HOLD>
 constexpr int stage_min_waves() { return (FLUX == FLUX_GODUNOV && EQ == EQ_EULER) ? 2 : (HOLD ? 6 : 1); }
 
-template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD>
+// HALO = 1: the split-buffer form. Arrays are subdomains with stored ghost layers on the axes
+// of g.hmask (Group), and the launch covers the box of tiles g.tlo + [0, g.tcnt) of each group;
+// the arithmetic per cell is the same as for the whole grid.
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD,
+          int HALO = 0>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stage_min_waves<EQ, FLUX, HOLD>(), 8)))
 stage_kernel(const StageArgs args)
 {
@@ -329,9 +347,16 @@ stage_kernel(const StageArgs args)
     const int32_t tile = (int32_t)(local % g.ntiles);
     if (!g.active[sample]) return;   // uniform across the workgroup
 
-    const int32_t tx = tile % g.tiles[0];
-    const int32_t ty = (tile / g.tiles[0]) % g.tiles[1];
-    const int32_t tz = tile / (g.tiles[0] * g.tiles[1]);
+    int32_t tx, ty, tz;
+    if constexpr (HALO) {
+        tx = g.tlo[0] + tile % g.tcnt[0];
+        ty = g.tlo[1] + (tile / g.tcnt[0]) % g.tcnt[1];
+        tz = g.tlo[2] + tile / (g.tcnt[0] * g.tcnt[1]);
+    } else {
+        tx = tile % g.tiles[0];
+        ty = (tile / g.tiles[0]) % g.tiles[1];
+        tz = tile / (g.tiles[0] * g.tiles[1]);
+    }
     const int32_t x0 = tx * BX, y0 = ty * BY, z0 = tz * BZ;
     const int32_t nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const int64_t sbase = (int64_t)sample * NF * g.cells;
@@ -348,7 +373,10 @@ stage_kernel(const StageArgs args)
         const int cz = c / (BX * BY);
         const int32_t gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
         cell_ok[k] = c < CELLS && gx < nx && gy < ny && gz < nz;
-        cell_g[k] = (gz * ny + gy) * nx + gx;   // cells < 2^31
+        if constexpr (HALO)
+            cell_g[k] = ((gz + g.off[2]) * g.pn[1] + (gy + g.off[1])) * g.pn[0] + (gx + g.off[0]);
+        else
+            cell_g[k] = (gz * ny + gy) * nx + gx;   // cells < 2^31
     }
     const double* un = g.un + sbase;
     double unr[CPT][NF];
@@ -365,10 +393,18 @@ stage_kernel(const StageArgs args)
                 const int px = e % PX;
                 const int py = (e / PX) % PY;
                 const int pz = e / (PX * PY);
-                const int32_t gx = wrap_index(x0 + px - G, nx, args.bc[0]);
-                const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - G, ny, args.bc[1]) : 0;
-                const int32_t gz = (DIM >= 3) ? wrap_index(z0 + pz - G, nz, args.bc[2]) : 0;
-                const int32_t gidx = (gz * ny + gy) * nx + gx;   // cells < 2^31
+                int32_t gidx;
+                if constexpr (HALO) {
+                    const int32_t ax = halo_index(x0 + px - G, nx, args.bc[0], g.off[0], g.pn[0], g.hmask & 1);
+                    const int32_t ay = (DIM >= 2) ? halo_index(y0 + py - G, ny, args.bc[1], g.off[1], g.pn[1], g.hmask & 2) : 0;
+                    const int32_t az = (DIM >= 3) ? halo_index(z0 + pz - G, nz, args.bc[2], g.off[2], g.pn[2], g.hmask & 4) : 0;
+                    gidx = (az * g.pn[1] + ay) * g.pn[0] + ax;
+                } else {
+                    const int32_t gx = wrap_index(x0 + px - G, nx, args.bc[0]);
+                    const int32_t gy = (DIM >= 2) ? wrap_index(y0 + py - G, ny, args.bc[1]) : 0;
+                    const int32_t gz = (DIM >= 3) ? wrap_index(z0 + pz - G, nz, args.bc[2]) : 0;
+                    gidx = (gz * ny + gy) * nx + gx;   // cells < 2^31
+                }
 #pragma unroll
                 for (int q = 0; q < NF; ++q) v[k][q] = src[q * g.cells + gidx];
             }
@@ -454,8 +490,9 @@ stage_kernel(const StageArgs args)
                               &g.bad[sample]);
 }
 
-// Wave speed and physicality of a state, without update (the step-0 reduction).
-template <int DIM, int EQ>
+// Wave speed and physicality of a state, without update (the step-0 reduction). HALO = 1:
+// over the owned cells of split-buffer subdomains (Group pn, off).
+template <int DIM, int EQ, int HALO = 0>
 __global__ void __launch_bounds__(kThreads)
 speed_kernel(const SpeedArgs args, int cells_per_block)
 {
@@ -464,17 +501,23 @@ speed_kernel(const SpeedArgs args, int cells_per_block)
     const int gi = find_group(args.g, args.ngroups, blk);
     const Group& g = args.g[gi];
     const int64_t local = blk - g.block0;
-    const int64_t per_sample = (g.cells + cells_per_block - 1) / cells_per_block;
+    const int64_t owned = HALO ? (int64_t)g.n[0] * g.n[1] * g.n[2] : g.cells;
+    const int64_t per_sample = (owned + cells_per_block - 1) / cells_per_block;
     const int32_t sample = (int32_t)(local / per_sample);
     const int64_t c0 = (local % per_sample) * cells_per_block;
     if (!g.active[sample]) return;
     const double* src = g.src + (int64_t)sample * NF * g.cells;
     double m = 0.0;
     bool bad = false;
-    for (int64_t c = c0 + threadIdx.x; c < c0 + cells_per_block && c < g.cells; c += kThreads) {
+    for (int64_t c = c0 + threadIdx.x; c < c0 + cells_per_block && c < owned; c += kThreads) {
+        int64_t a = c;
+        if constexpr (HALO) {
+            const int64_t x = c % g.n[0], y = (c / g.n[0]) % g.n[1], z = c / ((int64_t)g.n[0] * g.n[1]);
+            a = ((z + g.off[2]) * g.pn[1] + (y + g.off[1])) * g.pn[0] + (x + g.off[0]);
+        }
         double U[NF];
 #pragma unroll
-        for (int q = 0; q < NF; ++q) U[q] = src[q * g.cells + c];
+        for (int q = 0; q < NF; ++q) U[q] = src[q * g.cells + a];
         bool b;
         const double s = cell_speed<DIM, EQ>(U, g.ph, b);
         m = vmax(m, s);
@@ -485,29 +528,30 @@ speed_kernel(const SpeedArgs args, int cells_per_block)
                                 &g.bad[sample]);
 }
 
-template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD>
+template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT, int HOLD,
+          int HALO = 0>
 void launch_stage(const StageArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((stage_kernel<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, HOLD>),
+    hipLaunchKernelGGL((stage_kernel<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, HOLD, HALO>),
                        dim3((unsigned)a.nblocks), dim3(NT), 0, s, a);
 }
 
 constexpr int kSpeedCellsPerBlock = 4096;
 
-template <int DIM, int EQ>
+template <int DIM, int EQ, int HALO = 0>
 void launch_speed(const SpeedArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((speed_kernel<DIM, EQ>), dim3((unsigned)a.nblocks), dim3(kThreads), 0, s, a,
-                       kSpeedCellsPerBlock);
+    hipLaunchKernelGGL((speed_kernel<DIM, EQ, HALO>), dim3((unsigned)a.nblocks), dim3(kThreads), 0,
+                       s, a, kSpeedCellsPerBlock);
 }
 
 // Default LDS plan: split faces in 2D, fluxes held in registers otherwise.
 template <int DIM, int EQ, int RECON, int FLUX, int BX, int BY, int BZ, int NT,
-          int HOLD = (DIM == 2) ? 2 : 1>
+          int HOLD = (DIM == 2) ? 2 : 1, int HALO = 0>
 constexpr StageKernel make_stage_kernel()
 {
-    return StageKernel{&launch_stage<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, HOLD>,
-                       &launch_speed<DIM, EQ>, BX, BY, BZ, kSpeedCellsPerBlock};
+    return StageKernel{&launch_stage<DIM, EQ, RECON, FLUX, BX, BY, BZ, NT, HOLD, HALO>,
+                       &launch_speed<DIM, EQ, HALO>, BX, BY, BZ, kSpeedCellsPerBlock};
 }
 
 }  // namespace fvk

@@ -87,6 +87,15 @@ def _load():
         "fv_line_vjp": (i32, [vp, vp, vp, vp, i32, i64, vp]),
         "fv_profile_enable": (i32, [vp, i32]),
         "fv_profile_read": (i32, [vp, C.POINTER(dbl), C.POINTER(i64)]),
+        "fv_decomp_create": (i32, [vp, C.POINTER(i32), i64, C.POINTER(vp)]),
+        "fv_decomp_scatter": (i32, [vp, vp]),
+        "fv_decomp_gather": (i32, [vp, vp]),
+        "fv_decomp_advance": (i32, [vp, vp, dbl, dbl, i64, vp, vp, i32]),
+        "fv_decomp_profile_enable": (i32, [vp, i32]),
+        "fv_decomp_profile_read": (i32, [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(i64)]),
+        "fv_decomp_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64),
+                                 C.POINTER(i32), C.POINTER(i32)]),
+        "fv_decomp_destroy": (i32, [vp]),
         "fv_last_error": (C.c_char_p, []),
         "fv_version": (C.c_char_p, []),
     }
@@ -363,6 +372,57 @@ def fv_profile_read(solver):
     n = C.c_int64()
     check(lib.fv_profile_read(solver, C.byref(ms), C.byref(n)), "fv_profile_read")
     return ms.value, n.value
+
+
+def fv_decomp_create(solver, parts, batch) -> int:
+    h = C.c_void_p()
+    p = (C.c_int32 * 3)(*[int(x) for x in (list(parts) + [1, 1, 1])[:3]])
+    check(lib.fv_decomp_create(solver, p, int(batch), C.byref(h)), "fv_decomp_create")
+    return h.value
+
+
+def fv_decomp_scatter(d, state) -> None:
+    check(lib.fv_decomp_scatter(d, ptr(state)), "fv_decomp_scatter")
+
+
+def fv_decomp_gather(d, state) -> None:
+    check(lib.fv_decomp_gather(d, ptr(state)), "fv_decomp_gather")
+
+
+FV_DECOMP_OVERLAP, FV_DECOMP_DMA = 1, 2
+
+
+def fv_decomp_advance(d, t, t_end, cfl, nsteps, steps=None, err=None, overlap=True,
+                      dma=False) -> int:
+    mode = (FV_DECOMP_OVERLAP if overlap else 0) | (FV_DECOMP_DMA if dma else 0)
+    st = lib.fv_decomp_advance(d, ptr(t), float(t_end), float(cfl), int(nsteps), ptr(steps),
+                               ptr(err), mode)
+    if st in (FV_EINVAL, FV_ENOTSUP, FV_ENOMEM, FV_EDEVICE):
+        check(st, "fv_decomp_advance")
+    return st
+
+
+def fv_decomp_profile_enable(d, on: bool) -> None:
+    check(lib.fv_decomp_profile_enable(d, 1 if on else 0), "fv_decomp_profile_enable")
+
+
+def fv_decomp_profile_read(d):
+    a, b, n = C.c_double(), C.c_double(), C.c_int64()
+    check(lib.fv_decomp_profile_read(d, C.byref(a), C.byref(b), C.byref(n)), "fv_decomp_profile_read")
+    return a.value, b.value, n.value
+
+
+def fv_decomp_info(d):
+    ns, nm, ni, nsh = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    hb = C.c_int64()
+    check(lib.fv_decomp_info(d, C.byref(ns), C.byref(nm), C.byref(hb), C.byref(ni), C.byref(nsh)),
+          "fv_decomp_info")
+    return dict(subdomains=ns.value, messages=nm.value, halo_bytes_per_stage=hb.value,
+                interior_tiles=ni.value, shell_tiles=nsh.value)
+
+
+def fv_decomp_destroy(d) -> None:
+    check(lib.fv_decomp_destroy(d), "fv_decomp_destroy")
 
 
 def fv_version() -> str:
