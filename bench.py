@@ -11,7 +11,7 @@ state already resident in HBM), the roofline of the dominant kernel (the stage k
 timed with HIP events on the library's stream over its own launches) and the CPU oracle's
 rate on a bounded sample of the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh2d_ec4|kh3d|mc|sod|swe2d|mhd2d|mlmc|adjoint|halo]
+    python bench.py [--steps K] [--warmup W] [--workload kh2d|kh2d_roe|kh2d_godunov|kh2d_ec4|kh3d|mc|sod|swe2d|mhd2d|mlmc|adjoint|halo|stats]
     python bench.py --copy-calibration     # plain copy of known size, for rocprof counters
 """
 from __future__ import annotations
@@ -448,6 +448,72 @@ def run_halo(a):
     print(json.dumps(out))
 
 
+def run_stats(a):
+    """On-device Monte Carlo statistics of a batch of 1024 Kelvin--Helmholtz samples of 256^2
+    (WENO3 + HLLC + SSP-RK3, 20 steps from the seed-1912 initial data): the per-cell Welford
+    pass alone (max_h = 0) against the HBM roof (the state read once: 32 B per cell and sample,
+    plus the running moments read and written once per call), and the pass with the structure
+    functions S_q(h), h = 1..32, whose sums (a difference and a fused multiply-add per (cell,
+    axis, lag, quantity) term) are priced against the FP64 issue ceiling. Device time of each
+    call from HIP events on the caller's stream (the library's stream is ordered between them);
+    median of the timed calls after one untimed call."""
+    import numpy as np
+    import torch
+    import fv_inputs as fi
+    from paper_1912_07645_amd import Solver, Stats
+
+    B, n, H = 1024, 256, 32
+    K = a.steps if a.steps is not None else 5
+    dev = torch.device("cuda:0")
+    c, phi = fi.kh_coefficients(1912, np.arange(B))
+    s = Solver(dim=2, n=(n, n), eq="euler", flux="hllc", recon="weno3", integrator="ssprk3",
+               device=dev)
+    U = torch.from_numpy(fi.kh2d_state(n, c, phi)).to(dev)
+    t = torch.zeros(B, dtype=torch.float64, device=dev)
+    s.advance(U, t, 1e9, 0.4, 20)
+    cells = n * n
+    nq = s.num_quantities
+
+    def device_ms(st):
+        st.reset()
+        st.accumulate(U)
+        times = []
+        for _ in range(K):
+            st.reset()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            st.accumulate(U)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return float(np.median(times))
+
+    welford_ms = device_ms(Stats(s, max_h=0))
+    full_ms = device_ms(Stats(s, max_h=H))
+    bytes_welford = B * cells * nq * 8 + 2 * 2 * cells * nq * 8
+    terms = B * cells * 2 * H * nq
+    welford_gbs = bytes_welford / (welford_ms * 1e-3) / 1e9
+    sf_ms = full_ms - welford_ms
+    out = {
+        "metric": "MC statistics of a 1024 x 256^2 batch: device ms per batch", "value": full_ms,
+        "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": K, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "stats_kh2d_256x256_x1024_samples_lag32", "samples": B,
+                   "grid": [n, n], "quantities": nq, "max_h": H},
+        "welford_ms": welford_ms, "full_ms": full_ms,
+        "roofline": {"bound": "hbm", "kernel": "welford (max_h = 0)", "achieved": welford_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": welford_gbs / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_call": bytes_welford},
+        "structure_functions": {"bound": "alu", "ms": sf_ms, "terms": terms,
+                                "lane_ops_per_term": 2,
+                                "achieved": 2 * terms / (sf_ms * 1e-3) / 1e12,
+                                "peak": FP64_LANE_OPS_PEAK / 1e12, "unit": "T lane-ops/s",
+                                "frac": 2 * terms / (sf_ms * 1e-3) / FP64_LANE_OPS_PEAK},
+    }
+    print(json.dumps(out))
+
+
 def per_sample_rate(s, U, cfl, K, B1):
     """The same kernels with one sample per launch (the unbatched way), over B1 samples."""
     import torch
@@ -470,7 +536,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="kh2d", choices=sorted(WORKLOADS) + ["halo"])
+    ap.add_argument("--workload", default="kh2d", choices=sorted(WORKLOADS) + ["halo", "stats"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="kh2d only: skip the short batched-MC and adjoint measurements")
@@ -497,6 +563,9 @@ def main():
         return
     if a.workload == "halo":
         run_halo(a)
+        return
+    if a.workload == "stats":
+        run_stats(a)
         return
 
     out = measure(a, dict(WORKLOADS[a.workload]))

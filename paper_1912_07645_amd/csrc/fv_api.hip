@@ -992,11 +992,15 @@ extern "C" fv_status fv_stats_create(const fv_solver* s, int32_t max_h, fv_stats
     st->max_h = max_h;
     st->nq = s->nf;
     st->count = 0;
-    st->chunk = 64;
+    // samples per pass: with structure functions, the quantities of a chunk are staged in
+    // qbuf (chunk states); without, the whole batch goes through one Welford launch
+    const int64_t state_bytes = (int64_t)sizeof(double) * st->nq * s->cells;
+    st->chunk = max_h > 0 ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, (512ll << 20) / state_bytes))
+                          : (1 << 30);
     const size_t field = sizeof(double) * st->nq * s->cells;
     const size_t lags = sizeof(double) * st->nq * std::max(max_h, 1);
     const int32_t n32[3] = {(int32_t)s->grid.n[0], (int32_t)s->grid.n[1], (int32_t)s->grid.n[2]};
-    const int nblk = max_h > 0 ? sf_blocks_per_field(s->grid.dim, n32) : 0;
+    const int nblk = max_h > 0 ? sf_blocks_per_field(s->grid.dim, n32, max_h) : 0;
     bool ok = hipMalloc((void**)&st->mean, field) == hipSuccess &&
               hipMalloc((void**)&st->m2, field) == hipSuccess &&
               hipMalloc((void**)&st->s2mean, lags) == hipSuccess &&
@@ -1046,7 +1050,7 @@ extern "C" fv_status fv_stats_accumulate(fv_stats* st, const double* state, int6
     const int qkind = quantity_kind(s);
     const int64_t per = (int64_t)s->nf * s->cells;
     int32_t n32[3] = {(int32_t)s->grid.n[0], (int32_t)s->grid.n[1], (int32_t)s->grid.n[2]};
-    const int nblk = st->max_h > 0 ? sf_blocks_per_field(s->grid.dim, n32) : 0;
+    const int nblk = st->max_h > 0 ? sf_blocks_per_field(s->grid.dim, n32, st->max_h) : 0;
     const double denom = (double)s->grid.dim * (double)s->cells;
     for (int64_t b0 = 0; b0 < batch; b0 += st->chunk) {
         const int32_t nb = (int32_t)std::min<int64_t>(st->chunk, batch - b0);

@@ -29,7 +29,7 @@ void launch_welford_diff(int nf, int kind, const double* fine, const double* coa
 void launch_mlmc_combine(const CombineArgs& a, double* out, hipStream_t s);
 
 // Workgroups per (sample, quantity) of the structure-function pass.
-int sf_blocks_per_field(int32_t dim, const int32_t n[3]);
+int sf_blocks_per_field(int32_t dim, const int32_t n[3], int32_t max_h);
 // qout (may be null): also write the quantity fields of the batch, [sample][quantity][cells].
 void launch_welford(int nf, int kind, const double* state, int64_t cells, int32_t batch,
                     int64_t count0, double* mean, double* m2, double* qout, hipStream_t s);

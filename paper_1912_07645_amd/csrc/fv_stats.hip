@@ -5,70 +5,86 @@
 // Quantities: Euler (rho, u_1..u_dim, E) with u_k = m_k * (1 / rho); scalar: the field.
 #include "fv_stats.h"
 
+#include <algorithm>
+
 namespace fvk {
 
-// Per-cell Welford update over the samples of one batch, in sample order. One thread per
-// cell keeps the running moments of every quantity in registers. With qout, the quantity
-// fields of the samples are also written there ([sample][quantity][cells]) for the
-// structure functions, so the state is read once.
+// Per-cell Welford update over the samples of one batch, in sample order. A workgroup covers
+// 64 cells with one wavefront per quantity (64 NF threads): each thread keeps the running
+// moments of one (cell, quantity) in registers, so a batch has NF times as many wavefronts as
+// cells / 64. The loads of the next kWelfordDepth samples are issued before the current ones
+// are processed, so each thread has that many samples' loads in flight. With qout, the
+// quantities are also written there ([sample][quantity][cells]) for the structure functions.
 // KIND: 0 the field itself; 1 Euler (the momenta divided by rho); 2 shallow water (the
 // momenta divided by h); 3 ideal MHD (the three momenta divided by rho).
+constexpr int kWelfordDepth = 8;
+
 template <int NF, int KIND>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, int64_t count0,
                double* __restrict__ mean, double* __restrict__ m2, double* __restrict__ qout)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int D = kWelfordDepth;
+    const int q = threadIdx.x >> 6;   // the wavefront's quantity
+    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     if (c >= cells) return;
-    double mu[NF], s2[NF];
+    constexpr int DIV_END = (KIND == 1) ? NF - 1 : ((KIND == 3) ? 4 : NF);
+    const bool div = KIND != 0 && q >= 1 && q < DIV_END;   // uniform across the wavefront
+    const int64_t per = (int64_t)NF * cells;
+    const double* F = state + q * cells + c;
+    const double* R = state + c;
+    double mu = mean[q * cells + c], s2 = m2[q * cells + c];
+    double xc[D], rc[D];
 #pragma unroll
-    for (int q = 0; q < NF; ++q) {
-        mu[q] = mean[q * cells + c];
-        s2[q] = m2[q * cells + c];
+    for (int i = 0; i < D; ++i) {
+        xc[i] = (i < batch) ? F[i * per] : 0.0;
+        rc[i] = (div && i < batch) ? R[i * per] : 1.0;
     }
-    for (int32_t b = 0; b < batch; ++b) {
-        const double* U = state + (int64_t)b * NF * cells + c;
-        double x[NF];
+    for (int32_t b0 = 0; b0 < batch; b0 += D) {
+        double xn[D], rn[D];
 #pragma unroll
-        for (int q = 0; q < NF; ++q) x[q] = U[q * cells];
-        if (KIND != 0) {
-            const double ir = 1.0 / x[0];
-#pragma unroll
-            for (int q = 1; q < ((KIND == 1) ? NF - 1 : ((KIND == 3) ? 4 : NF)); ++q) x[q] = x[q] * ir;
+        for (int i = 0; i < D; ++i) {   // the next group's loads, before this group's work
+            const int32_t b = b0 + D + i;
+            xn[i] = (b < batch) ? F[b * per] : 0.0;
+            rn[i] = (div && b < batch) ? R[b * per] : 1.0;
         }
-        if (qout) {
-            double* Q = qout + (int64_t)b * NF * cells + c;
 #pragma unroll
-            for (int q = 0; q < NF; ++q) Q[q * cells] = x[q];
+        for (int i = 0; i < D; ++i) {
+            const int32_t b = b0 + i;
+            if (b < batch) {
+                const double x = div ? xc[i] * (1.0 / rc[i]) : xc[i];
+                if (qout) qout[b * per + q * cells + c] = x;
+                const double n = (double)(count0 + b + 1);
+                const double delta = x - mu;
+                mu = mu + (delta / n);
+                s2 = s2 + (delta * (x - mu));
+            }
         }
-        const double n = (double)(count0 + b + 1);
 #pragma unroll
-        for (int q = 0; q < NF; ++q) {
-            const double delta = x[q] - mu[q];
-            mu[q] = mu[q] + (delta / n);
-            s2[q] = s2[q] + (delta * (x[q] - mu[q]));
+        for (int i = 0; i < D; ++i) {
+            xc[i] = xn[i];
+            rc[i] = rn[i];
         }
     }
-#pragma unroll
-    for (int q = 0; q < NF; ++q) {
-        mean[q * cells + c] = mu[q];
-        m2[q * cells + c] = s2[q];
-    }
+    mean[q * cells + c] = mu;
+    m2[q * cells + c] = s2;
 }
 
 // Structure-function partial sums. Every line of cells along every axis is cut into segments
-// of kSfSeg cells; a thread takes kSfSegsPerThread segments and, lag after lag, accumulates
-// sum_cells (q(x + h e) - q(x))^2 over their cells. The values q(x + h e) of a segment form a
-// window that slides by one cell per lag, so each lag costs one new load per segment instead
-// of one per cell. Segments along y and z are dealt so that neighbouring lanes take
-// neighbouring lines (coalesced loads); along x, neighbouring lanes take neighbouring
-// segments of a row. Lags are taken kSfLagChunk at a time (register accumulators); each is
-// summed over the workgroup in a fixed order (wavefront shuffles, then the four wavefronts in
-// order) into one partial per workgroup. Grid: (workgroups per field, quantity, sample).
-constexpr int kSfSeg = 8;
-constexpr int kSfLagChunk = 16;
+// of kSfSeg cells; a thread takes kSfSegsPerThread segments and accumulates, kSfLag lags at a
+// time, sum_cells (q(x + h e) - q(x))^2 over their cells: the segment's values and the window
+// q(x0 + h0 .. x0 + h0 + kSfSeg + kSfLag - 2) are loaded first (no load waits on arithmetic),
+// then the kSfSeg x kSfLag terms run with compile-time indices. Segments along y and z are
+// dealt so that neighbouring lanes take neighbouring lines (coalesced loads); along x,
+// neighbouring lanes take neighbouring segments of a row. The chunk's lags are summed over
+// the workgroup in a fixed order through LDS (per lag: 16 runs of 16 threads, then the 16
+// run sums) into one partial per workgroup. Grid: (workgroups per field, quantity, sample).
+constexpr int kSfSeg = 16;
+constexpr int kSfLag = 16;
+constexpr int kSfWin = kSfSeg + kSfLag - 1;
 constexpr int kSfThreads = 256;
-constexpr int kSfSegsPerThread = 4;
+constexpr int kSfSegsPerThread = 2;
+constexpr int kSfRowLoads = (40 * 1024 / 8 + kSfThreads - 1) / kSfThreads;   // 20
 
 struct SfGeom {
     int32_t n[3];          // grid
@@ -78,7 +94,8 @@ struct SfGeom {
     int64_t items[4];      // first segment of axis d (items[dim] = total)
 };
 
-static SfGeom sf_geom(int32_t dim, const int32_t n[3])
+// Segments of the axes first..dim-1 (the x axis may be taken by the row kernel below).
+static SfGeom sf_geom(int32_t dim, const int32_t n[3], int first)
 {
     SfGeom g{};
     g.dim = dim;
@@ -89,18 +106,11 @@ static SfGeom sf_geom(int32_t dim, const int32_t n[3])
         g.lines[d] = cells / n[d];
         g.segs[d] = (n[d] + kSfSeg - 1) / kSfSeg;
         g.items[d] = acc;
-        if (d < dim) acc += g.lines[d] * g.segs[d];
+        if (d >= first && d < dim) acc += g.lines[d] * g.segs[d];
     }
     g.items[dim] = acc;
     for (int d = dim + 1; d < 4; ++d) g.items[d] = acc;
     return g;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, 64);
-    return v;
 }
 
 // Segment `item`: first cell base + x0 * stride along a line of nd cells, len cells in it.
@@ -142,71 +152,263 @@ __device__ __forceinline__ SfSeg sf_segment(const SfGeom& geo, int64_t item)
     return sg;
 }
 
-__global__ void __launch_bounds__(kSfThreads)
-sf_partial_kernel(const double* __restrict__ q, const SfGeom geo, int32_t nq, int32_t max_h,
-                  int32_t nblk, double* __restrict__ partial)
+// The workgroup's sums of the chunk's kSfLag lags, in a fixed order (8 lags at a time: the
+// 256 values of a lag in runs of 8, then the 32 run sums), stored as partial number blk_index
+// of lag h0 + l of the field whose partials start at out (out[(h - 1) * nblk + blk]).
+__device__ __forceinline__ void sf_block_store(const double (&acc)[kSfLag], double* red,
+                                               double* run, int h0, int max_h, double* out,
+                                               int64_t nblk, int64_t blk_index)
 {
-    __shared__ double red[kSfThreads / 64][kSfLagChunk];
-    const int64_t cells = (int64_t)geo.n[0] * geo.n[1] * geo.n[2];
-    const int blk = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
-    const double* Q = q + ((int64_t)b * nq + qi) * cells;
-    const int64_t item0 = (int64_t)blk * kSfThreads * kSfSegsPerThread + threadIdx.x;
-
-    for (int h0 = 1; h0 <= max_h; h0 += kSfLagChunk) {
-        double acc[kSfLagChunk];
 #pragma unroll
-        for (int l = 0; l < kSfLagChunk; ++l) acc[l] = 0.0;
-        for (int j = 0; j < kSfSegsPerThread; ++j) {
-            const SfSeg sg = sf_segment(geo, item0 + (int64_t)j * kSfThreads);
-            if (sg.len == 0) continue;
-            // base values q(x0 + r) (positions past the line wrap, and are masked)
-            double v0[kSfSeg], w[kSfSeg];
-            int32_t p = sg.x0;
+    for (int half = 0; half < kSfLag / 8; ++half) {
 #pragma unroll
-            for (int r = 0; r < kSfSeg; ++r) {
-                v0[r] = Q[sg.base + p * sg.stride];
-                p = (p + 1 == sg.nd) ? 0 : p + 1;
-            }
-            // window w[r] = q(x0 + r + h0)
-            p = sg.x0 + h0;
-            if (p >= sg.nd) p -= sg.nd;   // x0 < nd and h0 < nd
+        for (int l = 0; l < 8; ++l) red[l * kSfThreads + threadIdx.x] = acc[half * 8 + l];
+        __syncthreads();
+        {
+            const int l = threadIdx.x >> 5, r0 = (threadIdx.x & 31) * 8;
+            double v = red[l * kSfThreads + r0];
 #pragma unroll
-            for (int r = 0; r < kSfSeg; ++r) {
-                w[r] = Q[sg.base + p * sg.stride];
-                if (r + 1 < kSfSeg) p = (p + 1 == sg.nd) ? 0 : p + 1;
-            }
-#pragma unroll
-            for (int l = 0; l < kSfLagChunk; ++l) {
-                double a = acc[l];
-#pragma unroll
-                for (int r = 0; r < kSfSeg; ++r) {
-                    const double df = w[r] - v0[r];
-                    a = (r < sg.len) ? __builtin_fma(df, df, a) : a;
-                }
-                acc[l] = a;
-                if (l + 1 < kSfLagChunk) {   // slide the window by one cell
-#pragma unroll
-                    for (int r = 0; r + 1 < kSfSeg; ++r) w[r] = w[r + 1];
-                    p = (p + 1 == sg.nd) ? 0 : p + 1;
-                    w[kSfSeg - 1] = (h0 + l + 1 <= max_h) ? Q[sg.base + p * sg.stride] : 0.0;
-                }
-            }
-        }
-        // workgroup sums of the chunk's lags, in a fixed order
-#pragma unroll
-        for (int l = 0; l < kSfLagChunk; ++l) {
-            const double ws = wave_sum(acc[l]);
-            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][l] = ws;
+            for (int i = 1; i < 8; ++i) v = v + red[l * kSfThreads + r0 + i];
+            run[l * 32 + (threadIdx.x & 31)] = v;
         }
         __syncthreads();
-        if (threadIdx.x < kSfLagChunk && h0 + (int)threadIdx.x <= max_h) {
-            double s = red[0][threadIdx.x];
+        const int h = h0 + half * 8 + (int)threadIdx.x;
+        if (threadIdx.x < 8 && h <= max_h) {
+            double v = run[threadIdx.x * 32];
 #pragma unroll
-            for (int wv = 1; wv < kSfThreads / 64; ++wv) s = s + red[wv][threadIdx.x];
-            partial[(((int64_t)b * nq + qi) * max_h + (h0 + threadIdx.x - 1)) * nblk + blk] = s;
+            for (int i = 1; i < 32; ++i) v = v + run[threadIdx.x * 32 + i];
+            out[(int64_t)(h - 1) * nblk + blk_index] = v;
         }
         __syncthreads();
     }
+}
+
+// The sums along the lines of one segment: acc[l] += sum_{r < len} (w[r + l] - v0[r])^2, each
+// lag's terms in cell order.
+__device__ __forceinline__ void sf_segment_terms(const double (&v0)[kSfSeg],
+                                                 const double (&w)[kSfWin], int len,
+                                                 double (&acc)[kSfLag])
+{
+#pragma unroll
+    for (int r = 0; r < kSfSeg; ++r) {
+        if (r < len) {
+#pragma unroll
+            for (int l = 0; l < kSfLag; ++l) {
+                const double df = w[r + l] - v0[r];
+                acc[l] = __builtin_fma(df, df, acc[l]);
+            }
+        }
+    }
+}
+
+// Lines along y and z (and x when its rows do not fit the row kernel): segments read from
+// memory, neighbouring lanes on neighbouring lines (coalesced). Partials blk_off + blk.
+__global__ void __launch_bounds__(kSfThreads)
+sf_partial_kernel(const double* __restrict__ q, const SfGeom geo, int32_t nq, int32_t max_h,
+                  int32_t nblk, int32_t blk_off, double* __restrict__ partial)
+{
+    __shared__ double red[8 * kSfThreads];
+    __shared__ double run[8 * 32];
+    const int64_t cells = (int64_t)geo.n[0] * geo.n[1] * geo.n[2];
+    const int blk = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
+    const double* Q = q + ((int64_t)b * nq + qi) * cells;
+    double* out = partial + ((int64_t)b * nq + qi) * max_h * nblk;
+    const int64_t item0 = (int64_t)blk * kSfThreads * kSfSegsPerThread + threadIdx.x;
+
+    for (int h0 = 1; h0 <= max_h; h0 += kSfLag) {
+        // lags past max_h are summed as well and never stored (their window stays in the line)
+        double acc[kSfLag];
+#pragma unroll
+        for (int l = 0; l < kSfLag; ++l) acc[l] = 0.0;
+#pragma unroll 1   // one segment's values in registers at a time (3 wavefronts per SIMD)
+        for (int j = 0; j < kSfSegsPerThread; ++j) {
+            const SfSeg sg = sf_segment(geo, item0 + (int64_t)j * kSfThreads);
+            if (sg.len == 0) continue;
+            // 32-bit cell indices (a field has < 2^31 cells) off the workgroup's field base
+            const uint32_t base = (uint32_t)sg.base, stride = (uint32_t)sg.stride;
+            double v0[kSfSeg], w[kSfWin];
+#pragma unroll
+            for (int r = 0; r < kSfSeg; ++r)   // positions past a ragged line's end are skipped
+                v0[r] = Q[base + (uint32_t)(r < sg.len ? sg.x0 + r : sg.x0) * stride];
+            uint32_t p = (uint32_t)((sg.x0 + h0) % sg.nd);
+#pragma unroll
+            for (int k = 0; k < kSfWin; ++k) {
+                w[k] = Q[base + p * stride];
+                p = (p + 1 == (uint32_t)sg.nd) ? 0u : p + 1;
+            }
+            sf_segment_terms(v0, w, sg.len, acc);
+        }
+        sf_block_store(acc, red, run, h0, max_h, out, nblk, blk_off + blk);
+    }
+}
+
+// Staged lines. A workgroup takes 16 lines and 16 consecutive segments of each (256 cells),
+// and stages those cells plus the cells their lag windows reach (the periodic continuation,
+// so no wrap remains) in LDS with loads issued all at once; every thread then takes one
+// (line, segment) and reads its values and windows from LDS at fixed offsets. Lags up to
+// kSfStripLags (larger max_h: sf_partial_kernel).
+constexpr int kSfStripLines = 16;
+constexpr int kSfStripSegs = 16;
+constexpr int kSfStripSpan = kSfStripSegs * kSfSeg;                   // 256 cells per line
+constexpr int kSfStripLags = 64;
+constexpr int kSfStripExt = kSfStripSpan + kSfStripLags + kSfSeg;     // cells staged per line
+static_assert(kSfStripLines * kSfStripSegs == kSfThreads, "one (line, segment) per thread");
+
+// Lines along y or z: 16 lines adjacent in memory (consecutive x), stride S between a line's
+// cells; tile[e][c] = cell e of line c (lanes on neighbouring lines read neighbouring slots).
+// Blocks: (strip of 16 x, other coordinate, group of 16 segments); partials blk_off + blk.
+__global__ void __launch_bounds__(kSfThreads)
+sf_cols_kernel(const double* __restrict__ q, int32_t nx, int32_t L, int64_t S, int64_t other_stride,
+               int32_t strips_x, int32_t nother, int32_t groups, int32_t nq, int32_t max_h,
+               int32_t nblk, int32_t blk_off, int64_t cells, double* __restrict__ partial)
+{
+    __shared__ double tile[kSfStripExt * kSfStripLines];
+    __shared__ double red[8 * kSfThreads];
+    __shared__ double run[8 * 32];
+    const int blk = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
+    const int g = blk % groups, rest = blk / groups;
+    const int sx = rest % strips_x, o = rest / strips_x;
+    const int x0 = sx * kSfStripLines;
+    const int32_t P0 = g * kSfStripSpan;                      // first cell of the group
+    const int segs = (L + kSfSeg - 1) / kSfSeg;
+    const int chunks = (max_h + kSfLag - 1) / kSfLag;
+    const int ext = min(kSfStripExt, kSfStripSpan + chunks * kSfLag + kSfSeg);
+    const double* Q = q + ((int64_t)b * nq + qi) * cells + (int64_t)o * other_stride + x0;
+    double* out = partial + ((int64_t)b * nq + qi) * max_h * nblk;
+    {
+        constexpr int NL = kSfStripExt * kSfStripLines / kSfThreads;
+        double v[NL];
+        const int c = threadIdx.x & (kSfStripLines - 1);
+        const bool col_ok = x0 + c < nx;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = (threadIdx.x >> 4) + k * (kSfThreads / kSfStripLines);
+            if (e < ext && col_ok) {
+                int32_t p = P0 + e;
+                p = (p < L) ? p : p - L;
+                if (p >= L) p %= L;
+                v[k] = Q[(int64_t)p * S + c];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = (threadIdx.x >> 4) + k * (kSfThreads / kSfStripLines);
+            if (e < ext && col_ok) tile[e * kSfStripLines + c] = v[k];
+        }
+    }
+    __syncthreads();
+    const int c = threadIdx.x & (kSfStripLines - 1), sl = threadIdx.x >> 4;
+    const int sgi = g * kSfStripSegs + sl;
+    const bool ok = sgi < segs && x0 + c < nx;
+    const int len = ok ? min(kSfSeg, L - sgi * kSfSeg) : 0;
+    const double* T = tile + sl * kSfSeg * kSfStripLines + c;
+    for (int h0 = 1; h0 <= max_h; h0 += kSfLag) {
+        double acc[kSfLag];
+#pragma unroll
+        for (int l = 0; l < kSfLag; ++l) acc[l] = 0.0;
+        if (ok) {
+            double v0[kSfSeg], w[kSfWin];
+#pragma unroll
+            for (int i = 0; i < kSfSeg; ++i) v0[i] = T[i * kSfStripLines];
+            const double* W = T + h0 * kSfStripLines;
+#pragma unroll
+            for (int k = 0; k < kSfWin; ++k) w[k] = W[k * kSfStripLines];
+            sf_segment_terms(v0, w, len, acc);
+        }
+        sf_block_store(acc, red, run, h0, max_h, out, nblk, blk_off + blk);
+    }
+}
+
+// Lines along x (rows): 16 rows, each staged with element e at e + e / 16, so that the 16
+// segments of a row, which neighbouring lanes take, start 17 slots apart (different banks).
+// Blocks: (group of 16 rows, group of 16 segments); partials blk_off + blk.
+constexpr int kSfRowPitch = kSfStripExt + kSfStripExt / 16 + 1;
+
+__global__ void __launch_bounds__(kSfThreads)
+sf_rows_kernel(const double* __restrict__ q, int32_t L, int64_t rows, int32_t groups, int32_t nq,
+               int32_t max_h, int32_t nblk, int32_t blk_off, double* __restrict__ partial)
+{
+    __shared__ double tile[kSfStripLines * kSfRowPitch];
+    __shared__ double red[8 * kSfThreads];
+    __shared__ double run[8 * 32];
+    const int blk = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
+    const int g = blk % groups;
+    const int64_t row0 = (int64_t)(blk / groups) * kSfStripLines;
+    const int32_t P0 = g * kSfStripSpan;
+    const int segs = (L + kSfSeg - 1) / kSfSeg;
+    const int chunks = (max_h + kSfLag - 1) / kSfLag;
+    const int ext = min(kSfStripExt, kSfStripSpan + chunks * kSfLag + kSfSeg);
+    const int64_t cells = rows * L;
+    const double* Q = q + ((int64_t)b * nq + qi) * cells;
+    double* out = partial + ((int64_t)b * nq + qi) * max_h * nblk;
+    {
+        constexpr int PER = (kSfStripExt + kSfThreads - 1) / kSfThreads;   // loads per row
+        double v[kSfStripLines][PER];
+#pragma unroll
+        for (int r = 0; r < kSfStripLines; ++r)
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int e = threadIdx.x + j * kSfThreads;
+                if (e < ext && row0 + r < rows) {
+                    int32_t p = P0 + e;
+                    p = (p < L) ? p : p - L;
+                    if (p >= L) p %= L;
+                    v[r][j] = Q[(row0 + r) * L + p];
+                }
+            }
+#pragma unroll
+        for (int r = 0; r < kSfStripLines; ++r)
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int e = threadIdx.x + j * kSfThreads;
+                if (e < ext && row0 + r < rows) tile[r * kSfRowPitch + e + (e >> 4)] = v[r][j];
+            }
+    }
+    __syncthreads();
+    const int sl = threadIdx.x & (kSfStripSegs - 1), r = threadIdx.x >> 4;
+    const int sgi = g * kSfStripSegs + sl;
+    const bool ok = sgi < segs && row0 + r < rows;
+    const int len = ok ? min(kSfSeg, L - sgi * kSfSeg) : 0;
+    const double* T = tile + r * kSfRowPitch + 17 * sl;   // element 16 sl of the row
+    for (int h0 = 1, c = 0; h0 <= max_h; h0 += kSfLag, ++c) {
+        double acc[kSfLag];
+#pragma unroll
+        for (int l = 0; l < kSfLag; ++l) acc[l] = 0.0;
+        if (ok) {
+            // element 16 sl + m is at T[m + (m >> 4)]; for m = h0 + k, h0 = 1 + 16 c:
+            // (m >> 4) = c + ((1 + k) >> 4)
+            const double* W = T + h0 + c;
+            double v0[kSfSeg], w[kSfWin];
+#pragma unroll
+            for (int i = 0; i < kSfSeg; ++i) v0[i] = T[i];
+#pragma unroll
+            for (int k = 0; k < kSfWin; ++k) w[k] = W[k + ((1 + k) >> 4)];
+            sf_segment_terms(v0, w, len, acc);
+        }
+        sf_block_store(acc, red, run, h0, max_h, out, nblk, blk_off + blk);
+    }
+}
+
+// The staged kernels' blocks per field: rows, then y columns, then z columns (0 when max_h
+// exceeds the staged lags: the general kernel takes every axis then).
+struct SfStripPlan {
+    bool use;
+    int64_t rows_blocks, col_blocks[3];
+    int32_t groups[3], strips_x;
+};
+
+static SfStripPlan sf_strip_plan(int32_t dim, const int32_t n[3], int32_t max_h)
+{
+    SfStripPlan p{};
+    p.use = max_h <= kSfStripLags;
+    if (!p.use) return p;
+    for (int d = 0; d < dim; ++d) p.groups[d] = ((n[d] + kSfSeg - 1) / kSfSeg + kSfStripSegs - 1) / kSfStripSegs;
+    const int64_t rows = (int64_t)n[1] * n[2];
+    p.rows_blocks = (rows + kSfStripLines - 1) / kSfStripLines * p.groups[0];
+    p.strips_x = (n[0] + kSfStripLines - 1) / kSfStripLines;
+    if (dim >= 2) p.col_blocks[1] = (int64_t)p.strips_x * n[2] * p.groups[1];
+    if (dim >= 3) p.col_blocks[2] = (int64_t)p.strips_x * n[1] * p.groups[2];
+    return p;
 }
 
 // S_q(h) of every sample of the chunk: the workgroup partials of (sample, quantity, lag)
@@ -230,13 +432,29 @@ __global__ void sf_welford_kernel(const double* __restrict__ x, int32_t nq, int3
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int nt = nq * max_h;
     if (t >= nt) return;
+    constexpr int D = kWelfordDepth;
     double mu = s2mean[t], s2 = s2m2[t];
-    for (int32_t b = 0; b < batch; ++b) {
-        const double v = x[(int64_t)b * nt + t];
-        const double n = (double)(count0 + b + 1);
-        const double delta = v - mu;
-        mu = mu + (delta / n);
-        s2 = s2 + (delta * (v - mu));
+    double xc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xc[i] = (i < batch) ? x[(int64_t)i * nt + t] : 0.0;
+    for (int32_t b0 = 0; b0 < batch; b0 += D) {
+        double xn[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)   // the next group's loads, before this group's work
+            xn[i] = (b0 + D + i < batch) ? x[(int64_t)(b0 + D + i) * nt + t] : 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int32_t b = b0 + i;
+            if (b < batch) {
+                const double v = xc[i];
+                const double n = (double)(count0 + b + 1);
+                const double delta = v - mu;
+                mu = mu + (delta / n);
+                s2 = s2 + (delta * (v - mu));
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) xc[i] = xn[i];
     }
     s2mean[t] = mu;
     s2m2[t] = s2;
@@ -360,9 +578,11 @@ __global__ void fill_zero_kernel(double* __restrict__ p, int64_t n)
         p[i] = 0.0;
 }
 
-int sf_blocks_per_field(int32_t dim, const int32_t n[3])
+int sf_blocks_per_field(int32_t dim, const int32_t n[3], int32_t max_h)
 {
-    const SfGeom g = sf_geom(dim, n);
+    const SfStripPlan sp = sf_strip_plan(dim, n, max_h);
+    if (sp.use) return (int)(sp.rows_blocks + sp.col_blocks[1] + sp.col_blocks[2]);
+    const SfGeom g = sf_geom(dim, n, 0);
     const int64_t per = (int64_t)kSfThreads * kSfSegsPerThread;
     return (int)((g.items[dim] + per - 1) / per);
 }
@@ -371,8 +591,9 @@ template <int NF, int KIND>
 static void welford_launch(const double* state, int64_t cells, int32_t batch, int64_t count0,
                            double* mean, double* m2, double* qout, hipStream_t s)
 {
-    const unsigned nb = (unsigned)((cells + 255) / 256);
-    hipLaunchKernelGGL((welford_kernel<NF, KIND>), dim3(nb), dim3(256), 0, s, state, cells,
+    static_assert(NF * 64 <= 512, "one wavefront per quantity");
+    const unsigned nb = (unsigned)((cells + 63) / 64);
+    hipLaunchKernelGGL((welford_kernel<NF, KIND>), dim3(nb), dim3(64 * NF), 0, s, state, cells,
                        batch, count0, mean, m2, qout);
 }
 
@@ -391,10 +612,28 @@ void launch_welford(int nf, int kind, const double* state, int64_t cells, int32_
 void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t nq, int32_t max_h,
                        int32_t batch, double* partial, hipStream_t s)
 {
-    const SfGeom g = sf_geom(dim, n);
-    const int nblk = sf_blocks_per_field(dim, n);
-    hipLaunchKernelGGL(sf_partial_kernel, dim3(nblk, nq, batch), dim3(kSfThreads), 0, s, q, g, nq,
-                       max_h, nblk, partial);
+    const int nblk = sf_blocks_per_field(dim, n, max_h);
+    const SfStripPlan sp = sf_strip_plan(dim, n, max_h);
+    if (!sp.use) {
+        hipLaunchKernelGGL(sf_partial_kernel, dim3(nblk, nq, batch), dim3(kSfThreads), 0, s, q,
+                           sf_geom(dim, n, 0), nq, max_h, nblk, 0, partial);
+        return;
+    }
+    const int64_t cells = (int64_t)n[0] * n[1] * n[2];
+    hipLaunchKernelGGL(sf_rows_kernel, dim3((unsigned)sp.rows_blocks, nq, batch), dim3(kSfThreads),
+                       0, s, q, n[0], (int64_t)n[1] * n[2], sp.groups[0], nq, max_h, nblk, 0,
+                       partial);
+    int64_t off = sp.rows_blocks;
+    for (int d = 1; d < dim; ++d) {
+        const int64_t S = (d == 1) ? n[0] : (int64_t)n[0] * n[1];
+        // the other coordinate: z for y lines (stride nx ny), y for z lines (stride nx)
+        const int64_t other_stride = (d == 1) ? (int64_t)n[0] * n[1] : n[0];
+        const int32_t nother = (d == 1) ? n[2] : n[1];
+        hipLaunchKernelGGL(sf_cols_kernel, dim3((unsigned)sp.col_blocks[d], nq, batch),
+                           dim3(kSfThreads), 0, s, q, n[0], n[d], S, other_stride, sp.strips_x,
+                           nother, sp.groups[d], nq, max_h, nblk, (int)off, cells, partial);
+        off += sp.col_blocks[d];
+    }
 }
 
 void launch_sf_welford(const double* partial, int32_t nq, int32_t max_h, int32_t nblk,
