@@ -756,7 +756,7 @@ static void ghost_fill(const oc_problem* P, const oc_pad* pd, const double* U, d
     const int64_t N = cells_of(P);
     const int64_t PN = pd->m[0] * pd->m[1] * pd->m[2];
     for (int f = 0; f < nf; ++f) {
-        #pragma omp parallel for schedule(static)
+        #pragma omp parallel for collapse(2) schedule(static)
         for (int64_t kk = 0; kk < pd->m[2]; ++kk)
             for (int64_t jj = 0; jj < pd->m[1]; ++jj)
                 for (int64_t ii = 0; ii < pd->m[0]; ++ii) {
@@ -831,7 +831,7 @@ int oc_rhs(const oc_problem* P, const double* U, double* rhs)
          * (interior along the other axes). */
         for (int f = 0; f < nf; ++f) {
             const double* Wf = W + f * PN;
-            #pragma omp parallel for schedule(static)
+            #pragma omp parallel for collapse(2) schedule(static)
             for (int64_t k = -e[2]; k < nz + e[2]; ++k)
                 for (int64_t j = -e[1]; j < ny + e[1]; ++j)
                     for (int64_t i = -e[0]; i < nx + e[0]; ++i) {
@@ -845,7 +845,7 @@ int oc_rhs(const oc_problem* P, const double* U, double* rhs)
         const int64_t fx = nx + e[0], fy = ny + e[1], fz = nz + e[2];
         const int64_t NF = fx * fy * fz;
         const double a_inv = inv_dx(P, d);
-        #pragma omp parallel for schedule(static)
+        #pragma omp parallel for collapse(2) schedule(static)
         for (int64_t k = 0; k < fz; ++k)
             for (int64_t j = 0; j < fy; ++j)
                 for (int64_t i = 0; i < fx; ++i) {
@@ -865,7 +865,7 @@ int oc_rhs(const oc_problem* P, const double* U, double* rhs)
                     for (int f = 0; f < nf; ++f) Fh[f * NF + fi] = F[f];
                 }
         /* Step 4: flux difference along d, added in direction order x, y, z. */
-        #pragma omp parallel for schedule(static)
+        #pragma omp parallel for collapse(2) schedule(static)
         for (int64_t k = 0; k < nz; ++k)
             for (int64_t j = 0; j < ny; ++j)
                 for (int64_t i = 0; i < nx; ++i) {
