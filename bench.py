@@ -76,7 +76,7 @@ def algorithmic_bytes_per_cell_step(nf: int, integrator: str) -> int:
 WORKLOADS = {
     "kh2d": dict(name="kh2d_1024x1024_weno3_hllc_ssprk3", dim=2, n=1024, flux="hllc",
                  recon="weno3", integrator="ssprk3", cfl=0.4, batch=1, seed=1912,
-                 steps=2000, warmup=100, cpu_steps=8),
+                 steps=2000, warmup=100, cpu_steps=96),
     "kh3d": dict(name="kh3d_512^3_weno3_hllc_ssprk3", dim=3, n=512, flux="hllc",
                  recon="weno3", integrator="ssprk3", cfl=0.4, batch=1, seed=1914,
                  steps=20, warmup=2, cpu_steps=1),
