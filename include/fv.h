@@ -412,7 +412,7 @@ fv_status fv_line_vjp(fv_solver* solver, const double* lambda0, const double* dU
  * SSP-RK3 stepper; the Euler equations with WENO3 + HLLC (2D, 3D) or MUSCL + HLL or MUSCL +
  * Rusanov (2D) (FV_ENOTSUP otherwise, FV_EINVAL for bad sizes). It allocates the subdomain
  * arrays (cleared) for `batch` samples and the message buffers. The handle uses the solver's
- * stream and must not outlive the solver. */
+ * stream and must not outlive the solver; batch 1..8192. */
 typedef struct fv_decomp fv_decomp;  /* opaque, library-owned */
 fv_status fv_decomp_create(fv_solver* solver, const int32_t* parts, int64_t batch,
                            fv_decomp** out);

@@ -111,41 +111,37 @@ __global__ void decomp_copy_kernel(const DecompGeom geo, const double* __restric
     }
 }
 
-// Message element i -> (message, sample-field, slab cell); the slab cell's owned coordinates
-// in the sending subdomain (from = true) or in the receiving one's ghost layers.
+// Slab cell c of message m (x fastest within the slab) -> its array index in the sending
+// subdomain (from = true) or in the receiving one's ghost layers, for sample-field bq.
 __device__ __forceinline__ int64_t msg_array_index(const DecompGeom& geo, const HaloMsg& m,
-                                                   int64_t bq, int64_t c, bool from)
+                                                   int64_t bq, uint32_t c, bool from)
 {
-    int64_t l[3];
-    l[0] = c % m.e[0];
-    l[1] = (c / m.e[0]) % m.e[1];
-    l[2] = c / ((int64_t)m.e[0] * m.e[1]);
+    const uint32_t e0 = (uint32_t)m.e[0], e1 = (uint32_t)m.e[1];
+    int32_t l[3];
+    const uint32_t t = c / e0;
+    l[0] = (int32_t)(c - t * e0);
+    l[1] = (int32_t)(t % e1);
+    l[2] = (int32_t)(t / e1);
     const int a = m.axis;
     if (from) l[a] = (m.side == 0) ? l[a] : geo.nloc[a] - geo.g + l[a];
     else l[a] = (m.side == 0) ? geo.nloc[a] + l[a] : l[a] - geo.g;
-    return bq * geo.pcells + ((l[2] + geo.off[2]) * geo.pn[1] + (l[1] + geo.off[1])) * geo.pn[0] +
+    return bq * geo.pcells + ((int64_t)(l[2] + geo.off[2]) * geo.pn[1] + (l[1] + geo.off[1])) * geo.pn[0] +
            (l[0] + geo.off[0]);
 }
 
-__device__ __forceinline__ int find_msg(const HaloMsg* msg, int nmsg, int64_t i)
-{
-    int m = 0;
-    for (int k = 1; k < nmsg; ++k)
-        if (i >= msg[k].off) m = k;
-    return m;
-}
-
 // pack (dir 0): subdomain arrays -> send buffer; unpack (dir 1): receive buffer -> ghosts.
-__global__ void halo_kernel(const DecompGeom geo, const HaloMsg* __restrict__ msg, int64_t total,
-                            SubPtrs arr, double* __restrict__ buf, int dir)
+// Grid: (blocks over a slab's cells, message, sample * field); buffer layout
+// [message][sample][field][slab cell].
+__global__ void halo_kernel(const DecompGeom geo, const HaloMsg* __restrict__ msg, SubPtrs arr,
+                            double* __restrict__ buf, int dir)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const HaloMsg& m = msg[find_msg(msg, geo.nmsg, i)];
-        const int64_t r = i - m.off;
-        const int64_t c = r % m.cells, bq = r / m.cells;
-        if (dir == 0) buf[i] = arr.p[m.src][msg_array_index(geo, m, bq, c, true)];
-        else arr.p[m.dst][msg_array_index(geo, m, bq, c, false)] = buf[i];
+    const HaloMsg& m = msg[blockIdx.y];
+    const int64_t bq = blockIdx.z;
+    double* B = buf + m.off + bq * m.cells;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < (uint32_t)m.cells;
+         c += gridDim.x * blockDim.x) {
+        if (dir == 0) B[c] = arr.p[m.src][msg_array_index(geo, m, bq, c, true)];
+        else arr.p[m.dst][msg_array_index(geo, m, bq, c, false)] = B[c];
     }
 }
 
@@ -226,7 +222,7 @@ extern "C" fv_status fv_decomp_create(fv_solver* s, const int32_t* parts, int64_
 {
     if (!s || !parts || !out) return fail(FV_EINVAL, "NULL argument");
     *out = nullptr;
-    if (batch < 1 || batch > (1 << 20)) return fail(FV_EINVAL, "batch must be in [1, 2^20]");
+    if (batch < 1 || batch > 8192) return fail(FV_EINVAL, "batch must be in [1, 8192]");
     const int dim = s->grid.dim;
     int nsub = 1;
     for (int k = 0; k < 3; ++k) {
@@ -471,13 +467,22 @@ static void stage_launches(fv_decomp* d, const std::vector<Piece>& pieces, doubl
     }
 }
 
+// Grid of the pack / unpack kernel: enough blocks for the largest slab (at most 1024),
+// every message, every sample-field.
+static dim3 halo_grid(const fv_decomp* d)
+{
+    int64_t most = 1;
+    for (const HaloMsg& m : d->msgs) most = std::max<int64_t>(most, m.cells);
+    return dim3((unsigned)std::min<int64_t>(1024, (most + 255) / 256), (unsigned)d->msgs.size(),
+                (unsigned)(d->geo.nf * d->geo.batch));
+}
+
 static void exchange_start(fv_decomp* d, double* const* arr, hipEvent_t* cev, bool dma)
 {
     const fv_solver* s = d->s;
     const int64_t total = d->msg_doubles;
     if (total == 0) return;
-    const unsigned nb = (unsigned)std::min<int64_t>(2048, (total + 255) / 256);
-    hipLaunchKernelGGL(halo_kernel, dim3(nb), dim3(256), 0, s->stream, d->geo, d->msg_dev, total,
+    hipLaunchKernelGGL(halo_kernel, halo_grid(d), dim3(256), 0, s->stream, d->geo, d->msg_dev,
                        ptrs_of(arr, d->geo.nsub), d->send, 0);
     hipEventRecord(d->ev_pack, s->stream);
     hipStreamWaitEvent(d->copy, d->ev_pack, 0);
@@ -499,8 +504,7 @@ static void exchange_finish(fv_decomp* d, double* const* arr, hipStream_t str)
         hipEventRecord(d->ev_copy, d->copy);
         hipStreamWaitEvent(s->stream, d->ev_copy, 0);
     }
-    const unsigned nb = (unsigned)std::min<int64_t>(2048, (total + 255) / 256);
-    hipLaunchKernelGGL(halo_kernel, dim3(nb), dim3(256), 0, str, d->geo, d->msg_dev, total,
+    hipLaunchKernelGGL(halo_kernel, halo_grid(d), dim3(256), 0, str, d->geo, d->msg_dev,
                        ptrs_of(arr, d->geo.nsub), d->recv, 1);
 }
 
