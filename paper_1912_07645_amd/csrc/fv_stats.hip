@@ -152,34 +152,53 @@ __device__ __forceinline__ SfSeg sf_segment(const SfGeom& geo, int64_t item)
     return sg;
 }
 
-// The workgroup's sums of the chunk's kSfLag lags, in a fixed order (8 lags at a time: the
-// 256 values of a lag in runs of 8, then the 32 run sums), stored as partial number blk_index
-// of lag h0 + l of the field whose partials start at out (out[(h - 1) * nblk + blk]).
-__device__ __forceinline__ void sf_block_store(const double (&acc)[kSfLag], double* red,
-                                               double* run, int h0, int max_h, double* out,
+// The workgroup's sums of the chunk's kSfLag lags, stored as partial number blk_index of lag
+// h0 + l of the field whose partials start at out (out[(h - 1) * nblk + blk]). Fixed order:
+// within a wavefront a transposing butterfly over lane bits 5, 4, 3, 2 halves the lags a lane
+// holds at each step (the lane keeps the half its bit selects and adds the partner's copy of
+// it), so that lane i then holds lag i / 4 summed over 16 lanes; bits 1 and 0 finish the sums.
+// The wavefronts' sums meet in LDS (wsum[2][waves][kSfLag], alternate halves on alternate
+// chunks, so one barrier per chunk suffices) and are added in wavefront order.
+static_assert(kSfLag == 16 && kSfThreads % 64 == 0, "four halving steps over lane bits 5..2");
+constexpr int kSfWaves = kSfThreads / 64;
+
+__device__ __forceinline__ void sf_block_store(const double (&acc)[kSfLag], double* wsum,
+                                               int chunk, int h0, int max_h, double* out,
                                                int64_t nblk, int64_t blk_index)
 {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v8[8], v4[4], v2[2];
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-    for (int half = 0; half < kSfLag / 8; ++half) {
+    for (int k = 0; k < 8; ++k) {
+        const double keep = b5 ? acc[8 + k] : acc[k];
+        const double give = b5 ? acc[k] : acc[8 + k];
+        v8[k] = keep + __shfl_xor(give, 32);
+    }
 #pragma unroll
-        for (int l = 0; l < 8; ++l) red[l * kSfThreads + threadIdx.x] = acc[half * 8 + l];
-        __syncthreads();
-        {
-            const int l = threadIdx.x >> 5, r0 = (threadIdx.x & 31) * 8;
-            double v = red[l * kSfThreads + r0];
+    for (int k = 0; k < 4; ++k) {
+        const double keep = b4 ? v8[4 + k] : v8[k];
+        const double give = b4 ? v8[k] : v8[4 + k];
+        v4[k] = keep + __shfl_xor(give, 16);
+    }
 #pragma unroll
-            for (int i = 1; i < 8; ++i) v = v + red[l * kSfThreads + r0 + i];
-            run[l * 32 + (threadIdx.x & 31)] = v;
-        }
-        __syncthreads();
-        const int h = h0 + half * 8 + (int)threadIdx.x;
-        if (threadIdx.x < 8 && h <= max_h) {
-            double v = run[threadIdx.x * 32];
+    for (int k = 0; k < 2; ++k) {
+        const double keep = b3 ? v4[2 + k] : v4[k];
+        const double give = b3 ? v4[k] : v4[2 + k];
+        v2[k] = keep + __shfl_xor(give, 8);
+    }
+    double v = (b2 ? v2[1] : v2[0]) + __shfl_xor(b2 ? v2[0] : v2[1], 4);
+    v = v + __shfl_xor(v, 2);     // a + b and b + a are the same double
+    v = v + __shfl_xor(v, 1);
+    double* ws = wsum + (chunk & 1) * (kSfWaves * kSfLag);
+    if ((lane & 3) == 0) ws[wave * kSfLag + (lane >> 2)] = v;
+    __syncthreads();
+    const int h = h0 + (int)threadIdx.x;
+    if (threadIdx.x < kSfLag && h <= max_h) {
+        double t = ws[threadIdx.x];
 #pragma unroll
-            for (int i = 1; i < 32; ++i) v = v + run[threadIdx.x * 32 + i];
-            out[(int64_t)(h - 1) * nblk + blk_index] = v;
-        }
-        __syncthreads();
+        for (int w = 1; w < kSfWaves; ++w) t = t + ws[w * kSfLag + threadIdx.x];
+        out[(int64_t)(h - 1) * nblk + blk_index] = t;
     }
 }
 
@@ -207,15 +226,14 @@ __global__ void __launch_bounds__(kSfThreads)
 sf_partial_kernel(const double* __restrict__ q, const SfGeom geo, int32_t nq, int32_t max_h,
                   int32_t nblk, int32_t blk_off, double* __restrict__ partial)
 {
-    __shared__ double red[8 * kSfThreads];
-    __shared__ double run[8 * 32];
+    __shared__ double wsum[2 * kSfWaves * kSfLag];
     const int64_t cells = (int64_t)geo.n[0] * geo.n[1] * geo.n[2];
     const int blk = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
     const double* Q = q + ((int64_t)b * nq + qi) * cells;
     double* out = partial + ((int64_t)b * nq + qi) * max_h * nblk;
     const int64_t item0 = (int64_t)blk * kSfThreads * kSfSegsPerThread + threadIdx.x;
 
-    for (int h0 = 1; h0 <= max_h; h0 += kSfLag) {
+    for (int h0 = 1, ch = 0; h0 <= max_h; h0 += kSfLag, ++ch) {
         // lags past max_h are summed as well and never stored (their window stays in the line)
         double acc[kSfLag];
 #pragma unroll
@@ -238,7 +256,7 @@ sf_partial_kernel(const double* __restrict__ q, const SfGeom geo, int32_t nq, in
             }
             sf_segment_terms(v0, w, sg.len, acc);
         }
-        sf_block_store(acc, red, run, h0, max_h, out, nblk, blk_off + blk);
+        sf_block_store(acc, wsum, ch, h0, max_h, out, nblk, blk_off + blk);
     }
 }
 
@@ -263,8 +281,7 @@ sf_cols_kernel(const double* __restrict__ q, int32_t nx, int32_t L, int64_t S, i
                int32_t nblk, int32_t blk_off, int64_t cells, double* __restrict__ partial)
 {
     __shared__ double tile[kSfStripExt * kSfStripLines];
-    __shared__ double red[8 * kSfThreads];
-    __shared__ double run[8 * 32];
+    __shared__ double wsum[2 * kSfWaves * kSfLag];
     const int blk = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
     const int g = blk % groups, rest = blk / groups;
     const int sx = rest % strips_x, o = rest / strips_x;
@@ -302,7 +319,7 @@ sf_cols_kernel(const double* __restrict__ q, int32_t nx, int32_t L, int64_t S, i
     const bool ok = sgi < segs && x0 + c < nx;
     const int len = ok ? min(kSfSeg, L - sgi * kSfSeg) : 0;
     const double* T = tile + sl * kSfSeg * kSfStripLines + c;
-    for (int h0 = 1; h0 <= max_h; h0 += kSfLag) {
+    for (int h0 = 1, ch = 0; h0 <= max_h; h0 += kSfLag, ++ch) {
         double acc[kSfLag];
 #pragma unroll
         for (int l = 0; l < kSfLag; ++l) acc[l] = 0.0;
@@ -315,7 +332,7 @@ sf_cols_kernel(const double* __restrict__ q, int32_t nx, int32_t L, int64_t S, i
             for (int k = 0; k < kSfWin; ++k) w[k] = W[k * kSfStripLines];
             sf_segment_terms(v0, w, len, acc);
         }
-        sf_block_store(acc, red, run, h0, max_h, out, nblk, blk_off + blk);
+        sf_block_store(acc, wsum, ch, h0, max_h, out, nblk, blk_off + blk);
     }
 }
 
@@ -329,8 +346,7 @@ sf_rows_kernel(const double* __restrict__ q, int32_t L, int64_t rows, int32_t gr
                int32_t max_h, int32_t nblk, int32_t blk_off, double* __restrict__ partial)
 {
     __shared__ double tile[kSfStripLines * kSfRowPitch];
-    __shared__ double red[8 * kSfThreads];
-    __shared__ double run[8 * 32];
+    __shared__ double wsum[2 * kSfWaves * kSfLag];
     const int blk = blockIdx.x, qi = blockIdx.y, b = blockIdx.z;
     const int g = blk % groups;
     const int64_t row0 = (int64_t)(blk / groups) * kSfStripLines;
@@ -385,7 +401,7 @@ sf_rows_kernel(const double* __restrict__ q, int32_t L, int64_t rows, int32_t gr
             for (int k = 0; k < kSfWin; ++k) w[k] = W[k + ((1 + k) >> 4)];
             sf_segment_terms(v0, w, len, acc);
         }
-        sf_block_store(acc, red, run, h0, max_h, out, nblk, blk_off + blk);
+        sf_block_store(acc, wsum, c, h0, max_h, out, nblk, blk_off + blk);
     }
 }
 
