@@ -158,19 +158,27 @@ def kernel_sources_hash(workload: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per stage launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel sources (else None)."""
+def measured_traffic(workload: str, variant: int):
+    """HBM bytes per stage launch of tuner variant `variant` from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources and on that variant (else
+    None). The summary names its variant (`traffic_variant: N` before the figure, or the form
+    `traffic_bytes_per_launch[variant N]: X`)."""
     path = os.path.join(ROOT, "profiles", PROFILE_SUMMARY.get(workload, "-"))
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m_hash = re.search(r"sources_sha256:\s*([0-9a-f]+)", text)
-    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.e+]+)", text)
-    if not m_hash or not m_val or workload not in STAGE_KERNEL_UNIT \
+    if not m_hash or workload not in STAGE_KERNEL_UNIT \
             or m_hash.group(1) != kernel_sources_hash(workload):
         return None
-    return float(m_val.group(1))
+    by_variant = {}
+    m_var = re.search(r"traffic_variant:\s*(\d+)", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.e+]+)", text)
+    if m_var and m_val:
+        by_variant[int(m_var.group(1))] = float(m_val.group(1))
+    for v, x in re.findall(r"traffic_bytes_per_launch\[variant (\d+)\]:\s*([0-9.e+]+)", text):
+        by_variant[int(v)] = float(x)
+    return by_variant.get(int(variant))
 
 
 def cpu_baseline(w, U0, steps):
@@ -564,8 +572,9 @@ def main():
 
     ws = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or ws != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(each GPU would hold its own periodic subdomain; see the design notes)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(several GPUs would each hold a subdomain of the grid, with a halo exchange "
+              "between them every stage)",
               file=sys.stderr)
         sys.exit(2)
     if a.copy_calibration:
@@ -654,7 +663,7 @@ def measure(a, w, steps=None, warmup=None):
     achieved = bytes_per_launch / avg_launch_s / 1e9
     hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_per_launch,
-           "traffic": measured_traffic(a.workload)}
+           "traffic": measured_traffic(a.workload, tuned)}
     if w.get("eq", "euler") == "euler" and w["recon"] == "weno3" and w["flux"] in ("hllc", "roe"):
         ops_launch = lane_ops_per_cell_stage(w["dim"], w["integrator"], w["flux"]) * cells * B
         alu_tops = ops_launch / avg_launch_s / 1e12
