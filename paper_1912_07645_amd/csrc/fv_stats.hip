@@ -16,43 +16,68 @@ namespace fvk {
 // are processed, so each thread has that many samples' loads in flight. With qout, the
 // quantities are also written there ([sample][quantity][cells]) for the structure functions.
 // KIND: 0 the field itself; 1 Euler (the momenta divided by rho); 2 shallow water (the
-// momenta divided by h); 3 ideal MHD (the three momenta divided by rho).
+// momenta divided by h); 3 ideal MHD (the three momenta divided by rho). The divisor is field
+// 0. SHARE: its own wavefront, which loads it anyway, passes each group of samples' values to
+// the other wavefronts through LDS (two buffers, one barrier per group), so every field of a
+// sample is read from memory once; otherwise each dividing wavefront loads field 0 itself.
+// The launch without qout shares (fewer bytes: 400 us against 472 us for 1024 samples of 256^2
+// Euler); the one that writes the quantities does not (there the barrier costs more than the
+// re-reads: 251 us against 216 us for 256 samples).
 constexpr int kWelfordDepth = 8;
 
-template <int NF, int KIND>
+template <int NF, int KIND, bool SHARE>
 __global__ void __launch_bounds__(512)
 welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, int64_t count0,
                double* __restrict__ mean, double* __restrict__ m2, double* __restrict__ qout)
 {
+    static_assert(!SHARE || KIND != 0, "only quantities divided by field 0 share it");
     constexpr int D = kWelfordDepth;
+    __shared__ double f0[SHARE ? 2 * D * 64 : 1];   // [group parity][sample][cell]
     const int q = threadIdx.x >> 6;   // the wavefront's quantity
-    const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-    if (c >= cells) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = c < cells;      // lanes past the last cell only take part in barriers
+    if (!SHARE && !live) return;      // no barrier without SHARE: such lanes leave at once
     constexpr int DIV_END = (KIND == 1) ? NF - 1 : ((KIND == 3) ? 4 : NF);
     const bool div = KIND != 0 && q >= 1 && q < DIV_END;   // uniform across the wavefront
     const int64_t per = (int64_t)NF * cells;
-    const double* F = state + q * cells + c;
-    const double* R = state + c;
-    double mu = mean[q * cells + c], s2 = m2[q * cells + c];
-    double xc[D], rc[D];
+    const double* F = state + q * cells + (live ? c : 0);
+    const double* R = state + (live ? c : 0);
+    constexpr bool LOADR = KIND != 0 && !SHARE;   // dividing wavefronts load field 0 themselves
+    double mu = live ? mean[q * cells + c] : 0.0, s2 = live ? m2[q * cells + c] : 0.0;
+    double xc[D], rc[LOADR ? D : 1];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        xc[i] = (i < batch) ? F[i * per] : 0.0;
-        rc[i] = (div && i < batch) ? R[i * per] : 1.0;
+        xc[i] = (live && i < batch) ? F[i * per] : 0.0;
+        if constexpr (LOADR) rc[i] = (div && live && i < batch) ? R[i * per] : 1.0;
     }
-    for (int32_t b0 = 0; b0 < batch; b0 += D) {
-        double xn[D], rn[D];
+    for (int32_t b0 = 0, g = 0; b0 < batch; b0 += D, ++g) {
+        double xn[D], rn[LOADR ? D : 1];
 #pragma unroll
         for (int i = 0; i < D; ++i) {   // the next group's loads, before this group's work
             const int32_t b = b0 + D + i;
-            xn[i] = (b < batch) ? F[b * per] : 0.0;
-            rn[i] = (div && b < batch) ? R[b * per] : 1.0;
+            xn[i] = (live && b < batch) ? F[b * per] : 0.0;
+            if constexpr (LOADR) rn[i] = (div && live && b < batch) ? R[b * per] : 1.0;
+        }
+        double* sh = f0 + (SHARE ? (g & 1) * D * 64 : 0);
+        if constexpr (SHARE) {
+            // the buffer written here was last read before the previous group's barrier
+            if (q == 0) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) sh[i * 64 + lane] = xc[i];
+            }
+            __syncthreads();
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             const int32_t b = b0 + i;
-            if (b < batch) {
-                const double x = div ? xc[i] * (1.0 / rc[i]) : xc[i];
+            if (live && b < batch) {
+                double x = xc[i];
+                if constexpr (SHARE) {
+                    if (div) x = xc[i] * (1.0 / sh[i * 64 + lane]);
+                } else if constexpr (LOADR) {
+                    if (div) x = xc[i] * (1.0 / rc[i]);
+                }
                 if (qout) qout[b * per + q * cells + c] = x;
                 const double n = (double)(count0 + b + 1);
                 const double delta = x - mu;
@@ -63,11 +88,13 @@ welford_kernel(const double* __restrict__ state, int64_t cells, int32_t batch, i
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             xc[i] = xn[i];
-            rc[i] = rn[i];
+            if constexpr (LOADR) rc[i] = rn[i];
         }
     }
-    mean[q * cells + c] = mu;
-    m2[q * cells + c] = s2;
+    if (live) {
+        mean[q * cells + c] = mu;
+        m2[q * cells + c] = s2;
+    }
 }
 
 // Structure-function partial sums. Every line of cells along every axis is cut into segments
@@ -609,8 +636,13 @@ static void welford_launch(const double* state, int64_t cells, int32_t batch, in
 {
     static_assert(NF * 64 <= 512, "one wavefront per quantity");
     const unsigned nb = (unsigned)((cells + 63) / 64);
-    hipLaunchKernelGGL((welford_kernel<NF, KIND>), dim3(nb), dim3(64 * NF), 0, s, state, cells,
-                       batch, count0, mean, m2, qout);
+    constexpr bool SHARE = KIND != 0;
+    if (SHARE && !qout)
+        hipLaunchKernelGGL((welford_kernel<NF, KIND, SHARE>), dim3(nb), dim3(64 * NF), 0, s, state,
+                           cells, batch, count0, mean, m2, qout);
+    else
+        hipLaunchKernelGGL((welford_kernel<NF, KIND, false>), dim3(nb), dim3(64 * NF), 0, s, state,
+                           cells, batch, count0, mean, m2, qout);
 }
 
 void launch_welford(int nf, int kind, const double* state, int64_t cells, int32_t batch,
