@@ -150,12 +150,35 @@ def stage_kernel_sources(workload: str):
 
 
 def kernel_sources_hash(workload: str) -> str:
+    return sources_hash(stage_kernel_sources(workload))
+
+
+# The statistics pass: the sources of its kernels and the summary holding its counters.
+STATS_KERNEL_SOURCES = ("fv_common.h", "fv_stats.h", "fv_stats.hip")
+STATS_SUMMARY = "stats_mc_256x1024.md"
+
+
+def sources_hash(names) -> str:
     h = hashlib.sha256()
-    for name in stage_kernel_sources(workload):
+    for name in names:
         h.update(name.encode())
         with open(os.path.join(ROOT, "paper_1912_07645_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def measured_stats_traffic():
+    """HBM bytes of one whole-batch Welford launch from the committed counter summary, if it was
+    taken on the current sources of the statistics kernels (else None)."""
+    path = os.path.join(ROOT, "profiles", STATS_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"sources_sha256:\s*([0-9a-f]+)", text)
+    m_val = re.search(r"traffic_bytes_per_call:\s*([0-9.e+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != sources_hash(STATS_KERNEL_SOURCES):
+        return None
+    return float(m_val.group(1))
 
 
 def measured_traffic(workload: str, variant: int):
@@ -528,7 +551,8 @@ def run_stats(a):
         "welford_ms": welford_ms, "full_ms": full_ms,
         "roofline": {"bound": "hbm", "kernel": "welford (max_h = 0)", "achieved": welford_gbs,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": welford_gbs / HBM_PEAK_GBS,
-                     "traffic": None, "algorithmic_bytes_per_call": bytes_welford},
+                     "traffic": measured_stats_traffic(),
+                     "algorithmic_bytes_per_call": bytes_welford},
         "structure_functions": {"bound": "alu", "ms": sf_ms, "terms": terms,
                                 "lane_ops_per_term": 2,
                                 "achieved": 2 * terms / (sf_ms * 1e-3) / 1e12,

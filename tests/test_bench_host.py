@@ -40,3 +40,14 @@ def test_committed_headline_summary_covers_both_variants():
     if f"sources_sha256: {h}" in text:
         assert bench.measured_traffic("kh2d", 0) is not None
         assert bench.measured_traffic("kh2d", 1) is not None
+
+
+def test_stats_traffic_follows_the_statistics_sources(tmp_path, monkeypatch):
+    h = bench.sources_hash(bench.STATS_KERNEL_SOURCES)
+    _tree(tmp_path, monkeypatch, "")
+    (tmp_path / "profiles" / bench.STATS_SUMMARY).write_text(
+        f"sources_sha256: {h}\ntraffic_bytes_per_call: 123\n")
+    assert bench.measured_stats_traffic() == 123.0
+    (tmp_path / "profiles" / bench.STATS_SUMMARY).write_text(
+        "sources_sha256: 0123456789abcdef\ntraffic_bytes_per_call: 123\n")
+    assert bench.measured_stats_traffic() is None
