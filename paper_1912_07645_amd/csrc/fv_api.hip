@@ -992,8 +992,9 @@ extern "C" fv_status fv_stats_create(const fv_solver* s, int32_t max_h, fv_stats
     st->max_h = max_h;
     st->nq = s->nf;
     st->count = 0;
-    // samples per pass: with structure functions, the quantities of a chunk are staged in
-    // qbuf (chunk states); without, the whole batch goes through one Welford launch
+    // samples per pass: with structure functions, a chunk at a time (their partial sums); lags
+    // beyond the staged kernels' reach also stage the chunk's quantities in qbuf. Without,
+    // the whole batch goes through one Welford launch
     const int64_t state_bytes = (int64_t)sizeof(double) * st->nq * s->cells;
     st->chunk = max_h > 0 ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(256, (512ll << 20) / state_bytes))
                           : (1 << 30);
@@ -1006,7 +1007,7 @@ extern "C" fv_status fv_stats_create(const fv_solver* s, int32_t max_h, fv_stats
               hipMalloc((void**)&st->s2mean, lags) == hipSuccess &&
               hipMalloc((void**)&st->s2m2, lags) == hipSuccess;
     if (ok && max_h > 0)
-        ok = hipMalloc((void**)&st->qbuf, field * st->chunk) == hipSuccess &&
+        ok = (sf_staged(max_h) || hipMalloc((void**)&st->qbuf, field * st->chunk) == hipSuccess) &&
              hipMalloc((void**)&st->partial,
                        sizeof(double) * st->chunk * st->nq * max_h * (nblk + 1)) == hipSuccess;
     if (!ok) {
@@ -1055,10 +1056,17 @@ extern "C" fv_status fv_stats_accumulate(fv_stats* st, const double* state, int6
     for (int64_t b0 = 0; b0 < batch; b0 += st->chunk) {
         const int32_t nb = (int32_t)std::min<int64_t>(st->chunk, batch - b0);
         const double* chunk = state + b0 * per;
+        // the staged structure-function kernels form the quantities from the state themselves
+        const bool staged = st->max_h > 0 && sf_staged(st->max_h);
         launch_welford(s->nf, qkind, chunk, s->cells, nb, st->count, st->mean, st->m2,
-                       st->max_h > 0 ? st->qbuf : nullptr, str);
+                       (st->max_h > 0 && !staged) ? st->qbuf : nullptr, str);
         if (st->max_h > 0) {
-            launch_sf_partial(st->qbuf, s->grid.dim, n32, st->nq, st->max_h, nb, st->partial, str);
+            if (staged)
+                launch_sf_partial(chunk, s->grid.dim, n32, st->nq, st->max_h, nb, qkind,
+                                  st->partial, str);
+            else
+                launch_sf_partial(st->qbuf, s->grid.dim, n32, st->nq, st->max_h, nb, -1,
+                                  st->partial, str);
             // the per-sample values follow the partials in the same allocation
             double* xs = st->partial + (size_t)st->chunk * st->nq * st->max_h * nblk;
             launch_sf_welford(st->partial, st->nq, st->max_h, nblk, nb, st->count, denom, xs,

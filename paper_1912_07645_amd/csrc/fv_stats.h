@@ -33,8 +33,12 @@ int sf_blocks_per_field(int32_t dim, const int32_t n[3], int32_t max_h);
 // qout (may be null): also write the quantity fields of the batch, [sample][quantity][cells].
 void launch_welford(int nf, int kind, const double* state, int64_t cells, int32_t batch,
                     int64_t count0, double* mean, double* m2, double* qout, hipStream_t s);
+// Whether max_h lags run on the staged kernels, which can form the quantities themselves.
+bool sf_staged(int32_t max_h);
+// kind < 0: q holds the quantities ([sample][quantity][cells]). kind >= 0 (staged kernels
+// only): q is the state, and the quantities are formed from it as launch_welford forms them.
 void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t nq, int32_t max_h,
-                       int32_t batch, double* partial, hipStream_t s);
+                       int32_t batch, int kind, double* partial, hipStream_t s);
 // x: scratch of batch * nq * max_h doubles (S_q(h) of each sample of the chunk).
 void launch_sf_welford(const double* partial, int32_t nq, int32_t max_h, int32_t nblk,
                        int32_t batch, int64_t count0, double denom, double* x, double* s2mean,

@@ -305,7 +305,8 @@ static_assert(kSfStripLines * kSfStripSegs == kSfThreads, "one (line, segment) p
 __global__ void __launch_bounds__(kSfThreads)
 sf_cols_kernel(const double* __restrict__ q, int32_t nx, int32_t L, int64_t S, int64_t other_stride,
                int32_t strips_x, int32_t nother, int32_t groups, int32_t nq, int32_t max_h,
-               int32_t nblk, int32_t blk_off, int64_t cells, double* __restrict__ partial)
+               int32_t nblk, int32_t blk_off, int64_t cells, int32_t div_lo, int32_t div_hi,
+               double* __restrict__ partial)
 {
     __shared__ double tile[kSfStripExt * kSfStripLines];
     __shared__ double wsum[2 * kSfWaves * kSfLag];
@@ -318,26 +319,30 @@ sf_cols_kernel(const double* __restrict__ q, int32_t nx, int32_t L, int64_t S, i
     const int chunks = (max_h + kSfLag - 1) / kSfLag;
     const int ext = min(kSfStripExt, kSfStripSpan + chunks * kSfLag + kSfSeg);
     const double* Q = q + ((int64_t)b * nq + qi) * cells + (int64_t)o * other_stride + x0;
+    const double* R = q + (int64_t)b * nq * cells + (int64_t)o * other_stride + x0;   // field 0
+    const bool div = qi >= div_lo && qi < div_hi;   // uniform over the workgroup
     double* out = partial + ((int64_t)b * nq + qi) * max_h * nblk;
     {
         constexpr int NL = kSfStripExt * kSfStripLines / kSfThreads;
-        double v[NL];
+        double v[NL], r[NL];
         const int c = threadIdx.x & (kSfStripLines - 1);
         const bool col_ok = x0 + c < nx;
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int e = (threadIdx.x >> 4) + k * (kSfThreads / kSfStripLines);
+            r[k] = 1.0;
             if (e < ext && col_ok) {
                 int32_t p = P0 + e;
                 p = (p < L) ? p : p - L;
                 if (p >= L) p %= L;
                 v[k] = Q[(int64_t)p * S + c];
+                if (div) r[k] = R[(int64_t)p * S + c];
             }
         }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int e = (threadIdx.x >> 4) + k * (kSfThreads / kSfStripLines);
-            if (e < ext && col_ok) tile[e * kSfStripLines + c] = v[k];
+            if (e < ext && col_ok) tile[e * kSfStripLines + c] = div ? v[k] * (1.0 / r[k]) : v[k];
         }
     }
     __syncthreads();
@@ -370,7 +375,8 @@ constexpr int kSfRowPitch = kSfStripExt + kSfStripExt / 16 + 1;
 
 __global__ void __launch_bounds__(kSfThreads)
 sf_rows_kernel(const double* __restrict__ q, int32_t L, int64_t rows, int32_t groups, int32_t nq,
-               int32_t max_h, int32_t nblk, int32_t blk_off, double* __restrict__ partial)
+               int32_t max_h, int32_t nblk, int32_t blk_off, int32_t div_lo, int32_t div_hi,
+               double* __restrict__ partial)
 {
     __shared__ double tile[kSfStripLines * kSfRowPitch];
     __shared__ double wsum[2 * kSfWaves * kSfLag];
@@ -383,20 +389,24 @@ sf_rows_kernel(const double* __restrict__ q, int32_t L, int64_t rows, int32_t gr
     const int ext = min(kSfStripExt, kSfStripSpan + chunks * kSfLag + kSfSeg);
     const int64_t cells = rows * L;
     const double* Q = q + ((int64_t)b * nq + qi) * cells;
+    const double* R0 = q + (int64_t)b * nq * cells;   // field 0 of the sample
+    const bool div = qi >= div_lo && qi < div_hi;     // uniform over the workgroup
     double* out = partial + ((int64_t)b * nq + qi) * max_h * nblk;
     {
         constexpr int PER = (kSfStripExt + kSfThreads - 1) / kSfThreads;   // loads per row
-        double v[kSfStripLines][PER];
+        double v[kSfStripLines][PER], d[kSfStripLines][PER];
 #pragma unroll
         for (int r = 0; r < kSfStripLines; ++r)
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
                 const int e = threadIdx.x + j * kSfThreads;
+                d[r][j] = 1.0;
                 if (e < ext && row0 + r < rows) {
                     int32_t p = P0 + e;
                     p = (p < L) ? p : p - L;
                     if (p >= L) p %= L;
                     v[r][j] = Q[(row0 + r) * L + p];
+                    if (div) d[r][j] = R0[(row0 + r) * L + p];
                 }
             }
 #pragma unroll
@@ -404,7 +414,8 @@ sf_rows_kernel(const double* __restrict__ q, int32_t L, int64_t rows, int32_t gr
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
                 const int e = threadIdx.x + j * kSfThreads;
-                if (e < ext && row0 + r < rows) tile[r * kSfRowPitch + e + (e >> 4)] = v[r][j];
+                if (e < ext && row0 + r < rows)
+                    tile[r * kSfRowPitch + e + (e >> 4)] = div ? v[r][j] * (1.0 / d[r][j]) : v[r][j];
             }
     }
     __syncthreads();
@@ -657,12 +668,18 @@ void launch_welford(int nf, int kind, const double* state, int64_t cells, int32_
     else welford_launch<5, 1>(state, cells, batch, count0, mean, m2, qout, s);
 }
 
+bool sf_staged(int32_t max_h) { return max_h <= kSfStripLags; }
+
 void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t nq, int32_t max_h,
-                       int32_t batch, double* partial, hipStream_t s)
+                       int32_t batch, int kind, double* partial, hipStream_t s)
 {
     const int nblk = sf_blocks_per_field(dim, n, max_h);
     const SfStripPlan sp = sf_strip_plan(dim, n, max_h);
-    if (!sp.use) {
+    // quantities formed from the state as the Welford pass forms them: fields div_lo..div_hi-1
+    // divided by field 0
+    const int32_t div_lo = kind > 0 ? 1 : 0;
+    const int32_t div_hi = kind == 1 ? nq - 1 : (kind == 3 ? 4 : (kind == 2 ? nq : 0));
+    if (!sp.use) {   // sp.use == sf_staged(max_h): here q holds the quantities (kind < 0)
         hipLaunchKernelGGL(sf_partial_kernel, dim3(nblk, nq, batch), dim3(kSfThreads), 0, s, q,
                            sf_geom(dim, n, 0), nq, max_h, nblk, 0, partial);
         return;
@@ -670,7 +687,7 @@ void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t
     const int64_t cells = (int64_t)n[0] * n[1] * n[2];
     hipLaunchKernelGGL(sf_rows_kernel, dim3((unsigned)sp.rows_blocks, nq, batch), dim3(kSfThreads),
                        0, s, q, n[0], (int64_t)n[1] * n[2], sp.groups[0], nq, max_h, nblk, 0,
-                       partial);
+                       div_lo, div_hi, partial);
     int64_t off = sp.rows_blocks;
     for (int d = 1; d < dim; ++d) {
         const int64_t S = (d == 1) ? n[0] : (int64_t)n[0] * n[1];
@@ -679,7 +696,8 @@ void launch_sf_partial(const double* q, int32_t dim, const int32_t n[3], int32_t
         const int32_t nother = (d == 1) ? n[2] : n[1];
         hipLaunchKernelGGL(sf_cols_kernel, dim3((unsigned)sp.col_blocks[d], nq, batch),
                            dim3(kSfThreads), 0, s, q, n[0], n[d], S, other_stride, sp.strips_x,
-                           nother, sp.groups[d], nq, max_h, nblk, (int)off, cells, partial);
+                           nother, sp.groups[d], nq, max_h, nblk, (int)off, cells, div_lo, div_hi,
+                           partial);
         off += sp.col_blocks[d];
     }
 }
