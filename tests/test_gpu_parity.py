@@ -322,10 +322,15 @@ def test_statistics_match_oracle():
     (2, (29, 19), "euler", 18, 70),       # ragged along x and y, lags up to n_y - 1, two chunks
     (3, (12, 10, 9), "euler", 8, 5),      # all three axes
     (2, (16, 24), "burgers", 15, 3),      # whole segments, a scalar field
+    # lags above 64: the general kernel, reading the quantities the Welford pass writes
+    (2, (130, 70), "euler", 69, 6),
+    (1, (150,), "burgers", 100, 3),
 ])
 def test_structure_functions_match_oracle(dim, n, eq, H, B):
-    """S_q(h) for h = 1..H and its moments over samples against the oracle, on grids whose
-    lines end inside a segment, lags up to n - 1 on the shortest axis, every dimension."""
+    """Mean and variance of the quantities, and S_q(h) for h = 1..H with its moments over
+    samples, against the oracle, on grids whose lines end inside a segment, lags up to n - 1
+    on the shortest axis, every dimension; lags up to 64 run on the staged kernels (which form
+    the quantities from the state), longer ones on the general kernel."""
     torch = torch_gpu()
     from paper_1912_07645_amd import Stats
     p = O.Problem(dim=dim, n=n, eq=eq, flux="rusanov", recon="first_order",
@@ -339,6 +344,8 @@ def test_structure_functions_match_oracle(dim, n, eq, H, B):
     ref.accumulate(U0)
     assert out["count"] == ref.n == B
     assert_parity(out["mean"].cpu().numpy(), ref.mean, what="mean")
+    if B > 1:
+        assert_parity(out["var"].cpu().numpy(), ref.variance(), what="var")
     assert_parity(out["s2_mean"].cpu().numpy(), ref.s2(), bitwise=False, what="S2 mean")
     if B > 1:
         assert_parity(out["s2_var"].cpu().numpy(), ref.s2_variance(), tol=1e-10, bitwise=False,
