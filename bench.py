@@ -742,7 +742,8 @@ def measure(a, w, steps=None, warmup=None):
         mc = measure(ea, dict(WORKLOADS["mc"]), steps=20, warmup=2)
         out["batched_mc"] = {k: mc[k] for k in (
             "mc_sample_steps_per_s", "per_sample_launch_sample_steps_per_s",
-            "batched_speedup_over_per_sample_launches", "stats_ms_for_batch", "functionals")}
+            "batched_speedup_over_per_sample_launches", "stats_ms_for_batch", "stats_ms_timing",
+            "functionals")}
         out["batched_mc"]["config"] = mc["config"]["workload"]
         adj = run_adjoint(argparse.Namespace(steps=1, warmup=1, variant=None), WORKLOADS["adjoint"])
         out["adjoint"] = {k: adj[k] for k in ("forward_ms", "gradient_ms",
@@ -789,6 +790,8 @@ def measure(a, w, steps=None, warmup=None):
         res = st.read()
         torch.cuda.synchronize()
         out["stats_ms_for_batch"] = (time.perf_counter() - t0) * 1e3
+        out["stats_ms_timing"] = ("host clock around one accumulate and read of the batch; "
+                                  "bench.py --workload stats gives device-timed medians")
         out["functionals"] = functionals(s, U, cells, B)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, U0, w["cpu_steps"])
